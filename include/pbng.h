@@ -1,0 +1,145 @@
+/*
+ * pbng.h -- C ABI of the MI355X (gfx950) butterfly-peeling library.
+ *
+ * The library computes, for a simple bipartite graph G(W = (U, V), E):
+ *   - per-vertex and per-edge butterfly counts (Section 2.1, Algorithm 1),
+ *   - tip numbers of every vertex of one side (Section 2.2, Definition 2;
+ *     two-phase peeling of Section 3.2),
+ *   - wing numbers of every edge (Section 2.2, Definition 1; two-phase
+ *     peeling with the BE-Index of Sections 2.3 and 3.3, Algorithms 4-6).
+ * All counts, supports and results are uint64 and exact; they never depend
+ * on the number of partitions, the bound rule, tuning or batching.
+ *
+ * Graph format (pbng_csr): the U-side CSR.
+ *   row_ptr : int64[n_u + 1], row_ptr[0] == 0, row_ptr[n_u] == m,
+ *             non-decreasing.
+ *   col_idx : int32[m], V ids in [0, n_v), strictly increasing in each row
+ *             (no duplicate edges).
+ *   Edge id e is the CSR slot: edge e joins the row u with
+ *   row_ptr[u] <= e < row_ptr[u+1] to V-vertex col_idx[e].  Per-edge outputs
+ *   are in edge-id order.
+ *   on_device: 1 when row_ptr / col_idx are HIP device pointers; 0 for host
+ *   memory.  Output buffers live in the same memory space as the graph.
+ *
+ * Ownership: the caller owns the graph and every output buffer.  The library
+ * keeps no pointer to them after a call returns.  Work memory belongs to the
+ * context and is released by pbng_destroy.
+ *
+ * Synchronicity: every compute call enqueues on the context's stream and
+ * returns after the results are complete in the output buffers.
+ * Threads: a context must not be used by two host threads at once.
+ *
+ * Errors: functions return 0 on success or a negative PBNG_E_* code; the
+ * output contents are then unspecified.  pbng_last_error gives a message.
+ * No C++ exception crosses this interface.
+ */
+#ifndef PBNG_H
+#define PBNG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PBNG_OK 0
+#define PBNG_E_ARG (-1)         /* null pointer, negative size, bad enum    */
+#define PBNG_E_GRAPH (-2)       /* unsorted row, duplicate or out-of-range id */
+#define PBNG_E_NOMEM (-3)       /* device allocation failed                   */
+#define PBNG_E_DEVICE (-4)      /* HIP runtime error (see pbng_last_error)    */
+#define PBNG_E_OVERFLOW (-5)    /* size beyond the library's index widths     */
+#define PBNG_E_TIMEOUT (-6)     /* a bounded device wait did not finish       */
+#define PBNG_E_UNSUPPORTED (-7) /* option not available                       */
+
+typedef struct pbng_ctx pbng_ctx;
+
+typedef struct {
+    int64_t n_u, n_v, m;
+    const int64_t *row_ptr;
+    const int32_t *col_idx;
+    int32_t on_device;
+} pbng_csr;
+
+typedef enum {
+    PBNG_COUNT_VERTEX_U = 0, /* out: uint64[n_u], butterflies containing each u */
+    PBNG_COUNT_VERTEX_V = 1, /* out: uint64[n_v]                              */
+    PBNG_COUNT_EDGE = 2      /* out: uint64[m], butterflies containing each edge */
+} pbng_count_kind;
+
+typedef enum { PBNG_SIDE_U = 0, PBNG_SIDE_V = 1 } pbng_side;
+
+/* Bound rules for the coarse-grained ranges (Section 3.1.3).  Ranges only
+ * shape the schedule; results are identical under every rule.             */
+typedef enum {
+    PBNG_BOUND_PLAIN = 0,   /* the paper's work-estimate rule with adaptive
+                               target and scaling factor                    */
+    PBNG_BOUND_LEARNED = 1, /* predicted entity numbers from a loaded MLP;
+                               the plain rule when no predictor is loaded   */
+    PBNG_BOUND_RANDOM = 2   /* seeded random increasing bounds (tests)      */
+} pbng_bound_rule;
+
+/* flags */
+#define PBNG_F_NO_DYNAMIC 0x1   /* keep peeled entities in the lists (no
+                                   dynamic graph updates, Section 5.2)     */
+#define PBNG_F_NO_BATCH 0x2     /* tip: never recount; wing: per-edge update
+                                   instead of bloom-aggregated batches
+                                   (Section 5.1)                            */
+#define PBNG_F_NO_DENSE_TILE 0x4 /* counting: scalar path for hub pairs too */
+
+typedef struct {
+    int32_t P;          /* partitions; 0 = default (tip 150; wing 400 below
+                           1e8 edges, 1000 at or above), clamped to the
+                           work-efficiency bound of Section 4.2, minimum 1   */
+    int32_t bound_rule; /* pbng_bound_rule                                   */
+    int32_t flags;      /* PBNG_F_*                                          */
+    int32_t seed;       /* seed of PBNG_BOUND_RANDOM                         */
+    int32_t dense_cut;  /* degree above which hub pairs use the int8 matrix-
+                           core path in counting; 0 = library default,
+                           negative = never                                 */
+    int32_t reserved[3];
+} pbng_opts;
+
+/* Per-call counters and phase times of the last compute call. */
+typedef struct {
+    double ms_total, ms_prep, ms_count, ms_cd, ms_fd_prep, ms_fd;
+    uint64_t wedges;          /* wedges walked by all traversal kernels      */
+    uint64_t wedges_count;    /* of which by counting / recounting           */
+    uint64_t wedges_cd;       /* of which by coarse-grained peeling          */
+    uint64_t wedges_fd;       /* of which by fine-grained peeling            */
+    uint64_t updates;         /* support updates applied (wing)              */
+    uint64_t links;           /* bloom-edge links walked (wing)              */
+    uint64_t blooms, bloom_pairs; /* BE-Index size (wing)                    */
+    uint64_t rho;             /* coarse-grained peeling rounds (syncs)       */
+    uint64_t recounts;        /* tip rounds done by recounting (Section 5.1) */
+    int32_t partitions;       /* partitions actually created                 */
+    int32_t P_used;           /* partitions requested after clamping         */
+    uint64_t fd_work_max, fd_work_sum; /* estimated fine-grained work        */
+    uint64_t dense_pairs;     /* hub pairs counted on matrix cores           */
+} pbng_stats;
+
+/* Create a context bound to the current HIP device and the given stream
+ * (hipStream_t, may be NULL for the default stream).                      */
+int pbng_create(pbng_ctx **ctx, void *hip_stream);
+void pbng_destroy(pbng_ctx *ctx);
+const char *pbng_last_error(pbng_ctx *ctx);
+int pbng_last_stats(pbng_ctx *ctx, pbng_stats *out);
+
+/* Butterfly counts (Section 2.1, Algorithm 1; hub pairs optionally by an
+ * int8 matrix product on matrix cores).  out: see pbng_count_kind.        */
+int pbng_count(pbng_ctx *ctx, const pbng_csr *g, pbng_count_kind kind,
+               const pbng_opts *opts, uint64_t *out);
+
+/* Tip numbers of one side (Definition 2; Section 3.2).  tip_out: uint64
+ * [n_u] for PBNG_SIDE_U, [n_v] for PBNG_SIDE_V.  opts may be NULL.       */
+int pbng_tip(pbng_ctx *ctx, const pbng_csr *g, pbng_side side,
+             const pbng_opts *opts, uint64_t *tip_out);
+
+/* Wing numbers of every edge (Definition 1; Section 3.3, Algorithms 4-6).
+ * wing_out: uint64[m].  opts may be NULL.                                 */
+int pbng_wing(pbng_ctx *ctx, const pbng_csr *g, const pbng_opts *opts,
+              uint64_t *wing_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PBNG_H */

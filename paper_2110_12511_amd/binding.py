@@ -1,0 +1,242 @@
+"""Thin ctypes binding of libpbng.so (argument marshalling only).
+
+Every computation runs in the HIP library; this module only moves pointers
+and sizes across the C ABI declared in include/pbng.h.  It raises when the
+built library is missing: there is no fallback of any kind.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpbng.so")
+
+COUNT_VERTEX_U, COUNT_VERTEX_V, COUNT_EDGE = 0, 1, 2
+SIDE_U, SIDE_V = 0, 1
+BOUND_PLAIN, BOUND_LEARNED, BOUND_RANDOM = 0, 1, 2
+F_NO_DYNAMIC, F_NO_BATCH, F_NO_DENSE_TILE = 0x1, 0x2, 0x4
+
+ERRORS = {
+    -1: "PBNG_E_ARG",
+    -2: "PBNG_E_GRAPH",
+    -3: "PBNG_E_NOMEM",
+    -4: "PBNG_E_DEVICE",
+    -5: "PBNG_E_OVERFLOW",
+    -6: "PBNG_E_TIMEOUT",
+    -7: "PBNG_E_UNSUPPORTED",
+}
+
+
+class PbngError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Csr(ctypes.Structure):
+    _fields_ = [
+        ("n_u", ctypes.c_int64),
+        ("n_v", ctypes.c_int64),
+        ("m", ctypes.c_int64),
+        ("row_ptr", ctypes.c_void_p),
+        ("col_idx", ctypes.c_void_p),
+        ("on_device", ctypes.c_int32),
+    ]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [
+        ("P", ctypes.c_int32),
+        ("bound_rule", ctypes.c_int32),
+        ("flags", ctypes.c_int32),
+        ("seed", ctypes.c_int32),
+        ("dense_cut", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 3),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("ms_total", ctypes.c_double),
+        ("ms_prep", ctypes.c_double),
+        ("ms_count", ctypes.c_double),
+        ("ms_cd", ctypes.c_double),
+        ("ms_fd_prep", ctypes.c_double),
+        ("ms_fd", ctypes.c_double),
+        ("wedges", ctypes.c_uint64),
+        ("wedges_count", ctypes.c_uint64),
+        ("wedges_cd", ctypes.c_uint64),
+        ("wedges_fd", ctypes.c_uint64),
+        ("updates", ctypes.c_uint64),
+        ("links", ctypes.c_uint64),
+        ("blooms", ctypes.c_uint64),
+        ("bloom_pairs", ctypes.c_uint64),
+        ("rho", ctypes.c_uint64),
+        ("recounts", ctypes.c_uint64),
+        ("partitions", ctypes.c_int32),
+        ("P_used", ctypes.c_int32),
+        ("fd_work_max", ctypes.c_uint64),
+        ("fd_work_sum", ctypes.c_uint64),
+        ("dense_pairs", ctypes.c_uint64),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+EXPORTS = ["pbng_create", "pbng_destroy", "pbng_last_error", "pbng_last_stats", "pbng_count", "pbng_tip", "pbng_wing"]
+
+_lib = None
+
+
+def load():
+    """Load libpbng.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() or python -m paper_2110_12511_amd.build")
+    # PyTorch ships its own HIP runtime.  Importing it first makes the dynamic
+    # loader bind this library to that same runtime, so device pointers and
+    # streams from torch are valid here (one HIP runtime per process).
+    import torch  # noqa: F401
+
+    lib = ctypes.CDLL(LIB_PATH)
+    vp = ctypes.c_void_p
+    lib.pbng_create.argtypes = [ctypes.POINTER(vp), vp]
+    lib.pbng_create.restype = ctypes.c_int
+    lib.pbng_destroy.argtypes = [vp]
+    lib.pbng_destroy.restype = None
+    lib.pbng_last_error.argtypes = [vp]
+    lib.pbng_last_error.restype = ctypes.c_char_p
+    lib.pbng_last_stats.argtypes = [vp, ctypes.POINTER(Stats)]
+    lib.pbng_last_stats.restype = ctypes.c_int
+    lib.pbng_count.argtypes = [vp, ctypes.POINTER(Csr), ctypes.c_int, ctypes.POINTER(Opts), vp]
+    lib.pbng_count.restype = ctypes.c_int
+    lib.pbng_tip.argtypes = [vp, ctypes.POINTER(Csr), ctypes.c_int, ctypes.POINTER(Opts), vp]
+    lib.pbng_tip.restype = ctypes.c_int
+    lib.pbng_wing.argtypes = [vp, ctypes.POINTER(Csr), ctypes.POINTER(Opts), vp]
+    lib.pbng_wing.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def make_opts(P=0, bound_rule=BOUND_PLAIN, flags=0, seed=0, dense_cut=0) -> Opts:
+    o = Opts()
+    o.P, o.bound_rule, o.flags, o.seed, o.dense_cut = int(P), int(bound_rule), int(flags), int(seed), int(dense_cut)
+    return o
+
+
+class Context:
+    """One library context on the current HIP device and a stream (or NULL)."""
+
+    def __init__(self, stream_ptr: int | None = None):
+        self.lib = load()
+        self.h = ctypes.c_void_p()
+        rc = self.lib.pbng_create(ctypes.byref(self.h), ctypes.c_void_p(stream_ptr) if stream_ptr else None)
+        if rc:
+            raise PbngError(rc, "pbng_create failed")
+
+    def close(self):
+        if self.h:
+            self.lib.pbng_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc:
+            raise PbngError(rc, self.lib.pbng_last_error(self.h).decode())
+
+    def stats(self) -> dict:
+        s = Stats()
+        self._check(self.lib.pbng_last_stats(self.h, ctypes.byref(s)))
+        return s.as_dict()
+
+    # raw pointer calls -------------------------------------------------
+    def count_raw(self, csr: Csr, kind: int, out_ptr: int, opts: Opts | None = None):
+        self._check(self.lib.pbng_count(self.h, ctypes.byref(csr), kind, ctypes.byref(opts) if opts else None,
+                                        ctypes.c_void_p(out_ptr)))
+
+    def tip_raw(self, csr: Csr, side: int, out_ptr: int, opts: Opts | None = None):
+        self._check(self.lib.pbng_tip(self.h, ctypes.byref(csr), side, ctypes.byref(opts) if opts else None,
+                                      ctypes.c_void_p(out_ptr)))
+
+    def wing_raw(self, csr: Csr, out_ptr: int, opts: Opts | None = None):
+        self._check(self.lib.pbng_wing(self.h, ctypes.byref(csr), ctypes.byref(opts) if opts else None,
+                                       ctypes.c_void_p(out_ptr)))
+
+
+# ---------------------------------------------------------------- graphs
+
+class DeviceGraph:
+    """A U-side CSR resident in device memory (torch tensors as storage)."""
+
+    def __init__(self, n_u, n_v, row_ptr, col_idx):
+        import torch
+
+        self.n_u, self.n_v = int(n_u), int(n_v)
+        self.row_ptr = torch.as_tensor(np.ascontiguousarray(row_ptr, dtype=np.int64)).to("cuda")
+        self.col_idx = torch.as_tensor(np.ascontiguousarray(col_idx, dtype=np.int32)).to("cuda")
+        self.m = int(self.col_idx.numel())
+
+    @classmethod
+    def from_graph(cls, g):
+        return cls(g.n_u, g.n_v, g.row_ptr, g.col_idx)
+
+    def csr(self) -> Csr:
+        c = Csr()
+        c.n_u, c.n_v, c.m = self.n_u, self.n_v, self.m
+        c.row_ptr = self.row_ptr.data_ptr()
+        c.col_idx = self.col_idx.data_ptr() if self.m else 0
+        c.on_device = 1
+        return c
+
+
+def host_csr(n_u, n_v, row_ptr: np.ndarray, col_idx: np.ndarray) -> Csr:
+    c = Csr()
+    c.n_u, c.n_v, c.m = int(n_u), int(n_v), int(col_idx.shape[0])
+    c.row_ptr = row_ptr.ctypes.data
+    c.col_idx = col_idx.ctypes.data if col_idx.shape[0] else 0
+    c.on_device = 0
+    return c
+
+
+def _out_tensor(n):
+    import torch
+
+    return torch.zeros(max(int(n), 1), dtype=torch.uint64, device="cuda")
+
+
+def count(ctx: Context, dg: DeviceGraph, kind: int, opts: Opts | None = None):
+    n = dg.n_u if kind == COUNT_VERTEX_U else (dg.n_v if kind == COUNT_VERTEX_V else dg.m)
+    out = _out_tensor(n)
+    ctx.count_raw(dg.csr(), kind, out.data_ptr(), opts)
+    return out[:n]
+
+
+def tip(ctx: Context, dg: DeviceGraph, side: int, opts: Opts | None = None):
+    n = dg.n_u if side == SIDE_U else dg.n_v
+    out = _out_tensor(n)
+    ctx.tip_raw(dg.csr(), side, out.data_ptr(), opts)
+    return out[:n]
+
+
+def wing(ctx: Context, dg: DeviceGraph, opts: Opts | None = None):
+    out = _out_tensor(dg.m)
+    ctx.wing_raw(dg.csr(), out.data_ptr(), opts)
+    return out[: dg.m]
+
+
+def to_numpy_u64(t) -> np.ndarray:
+    """uint64 device tensor -> numpy (via int64 view: torch lacks uint64 copies on some builds)."""
+    import torch
+
+    return t.view(torch.int64).cpu().numpy().view(np.uint64)

@@ -1,0 +1,659 @@
+// Butterfly counting by priority wedge traversal (Algorithm 1) and BE-Index
+// construction inside the same traversal (Section 2.3, "Construction").
+//
+// For a start vertex s (a label), every wedge s -> mid -> last with
+// last < min(s, mid) is walked; the lasts of one mid form the prefix of the
+// sorted N_mid whose length prep stored in lpl.  wc[last] counts the wedges
+// per (s, last).  A (s, last) pair with wc >= 2 is one maximal priority bloom
+// with bloom number wc; its C(wc, 2) butterflies contain s and last once each
+// and every mid wc - 1 times; the edges (s, mid) and (mid, last) of each of
+// its wedges are twins and each lies in wc - 1 of its butterflies.
+//
+// Work mapping: starts are binned by their wedge count W_s.
+//   small  (W_s <= 512)  : one 64-lane workgroup per start, LDS hash
+//   medium (W_s <= 4096) : one 256-lane workgroup per start, LDS hash
+//   large                : persistent 256-lane workgroups, each with a dense
+//                          counter array over all labels in HBM plus a list of
+//                          the labels it touched
+// Inside a start, the (mid, prefix) segments are processed BLOCK at a time:
+// a block scan of the prefix lengths lets each lane pick its wedges by a
+// binary search over the segment starts, so consecutive lanes read
+// consecutive entries of the same N_mid whatever the degree mix.
+#include "pbng_internal.h"
+
+#include <algorithm>
+
+namespace pbng {
+
+enum : int {
+    M_VERTEX = 1,   // per-vertex supports (by label)
+    M_EDGE = 2,     // per-edge supports (by edge id)
+    M_BE_SIZE = 4,  // count blooms / pairs per start
+    M_BE_FILL = 8,  // emit blooms and twin pairs (and per-edge supports)
+};
+
+constexpr u32 NO_BLOOM = 0xFFFFFFFFu;
+
+struct CountArgs {
+    const i64 *loff;
+    const i32 *ladj, *leid, *lpl;
+    const i64 *wsum;             // wedges per start (upper bound when filtered)
+    const unsigned char *alive;  // by label; null = all alive
+    u64 *sup_label;              // M_VERTEX
+    u64 *sup_edge;               // M_EDGE / M_BE_FILL
+    const i32 *starts;           // work list of this bin
+    i64 nstarts;
+    u32 *next;                   // work counter
+    i64 *bcnt, *pcnt;            // M_BE_SIZE: per start
+    const i64 *bbase, *pbase;    // M_BE_FILL: exclusive prefix per start
+    i64 *boff;                   // M_BE_FILL: first pair of each bloom
+    u32 *bk;                     // M_BE_FILL: bloom number
+    i32 *bedge;                  // M_BE_FILL: twin pairs (2 edge ids per pair)
+    i32 *pbloom;                 // M_BE_FILL: bloom of each pair
+    u32 *dcnt;                   // dense accumulators [slots * n]
+    i32 *dbid;                   // [slots * n]
+    i32 *dtouch;                 // [slots * n]
+    u32 *dntouch;                // [slots]
+    i64 n;
+    u64 *wedges;                 // wedges walked
+};
+
+__device__ __forceinline__ u32 hash32(u32 x) { return x * 2654435761u; }
+
+template <int BLOCK>
+__device__ __forceinline__ i32 block_incl_scan_i32(i32 v, i32 *sh_wave, i32 &total) {
+    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+    i32 x = v;
+    for (int d = 1; d < WAVE; d <<= 1) {
+        i32 y = __shfl_up(x, d, WAVE);
+        if (lane >= d) x += y;
+    }
+    if (BLOCK == WAVE) {
+        total = __shfl(x, WAVE - 1, WAVE);
+        return x;
+    }
+    if (lane == WAVE - 1) sh_wave[wid] = x;
+    __syncthreads();
+    i32 off = 0, tot = 0;
+    for (int w = 0; w < BLOCK / WAVE; ++w) {
+        i32 t = sh_wave[w];
+        if (w < wid) off += t;
+        tot += t;
+    }
+    __syncthreads();
+    total = tot;
+    return x + off;
+}
+
+template <int BLOCK>
+__device__ __forceinline__ u64 block_sum_u64(u64 v, u64 *sh) {
+    for (int d = WAVE / 2; d > 0; d >>= 1) v += __shfl_down(v, d, WAVE);
+    if (BLOCK == WAVE) return __shfl(v, 0, WAVE);
+    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    u64 t = 0;
+    for (int w = 0; w < BLOCK / WAVE; ++w) t += sh[w];
+    __syncthreads();
+    return t;
+}
+
+// ------------------------------------------------------------------ accumulators
+// Both expose: add(key); entries(); entry(i, key, cnt) (key < 0: empty);
+// handle(i) of entry i; find(key) -> handle; cnt(h); set_cnt(h, v);
+// inc(h) (atomic, returns old); set_bid(h, b); bid(h); reset(tid).
+
+// Open-addressing hash in LDS, linear probing, key -1 = empty.
+struct LdsAcc {
+    i32 *keys;
+    u32 *vals;
+    i32 *bids;
+    u32 mask;
+    int shift;
+    __device__ void init(int logcap, int tid, int nthreads) {
+        mask = (1u << logcap) - 1;
+        shift = 32 - logcap;
+        for (u32 i = tid; i <= mask; i += nthreads) {
+            keys[i] = -1;
+            vals[i] = 0;
+        }
+    }
+    __device__ __forceinline__ void add(i32 key) {
+        u32 h = hash32((u32)key) >> shift;
+        for (;;) {
+            i32 k = keys[h];
+            if (k == key) break;
+            if (k == -1) {
+                i32 prev = atomicCAS(&keys[h], -1, key);
+                if (prev == -1 || prev == key) break;
+            }
+            h = (h + 1) & mask;
+        }
+        atomicAdd(&vals[h], 1u);
+    }
+    __device__ __forceinline__ i64 entries() const { return (i64)mask + 1; }
+    __device__ __forceinline__ void entry(i64 i, i32 &key, u32 &c) const {
+        key = keys[i];
+        c = vals[i];
+    }
+    __device__ __forceinline__ u32 handle(i64 i) const { return (u32)i; }
+    __device__ __forceinline__ u32 find(i32 key) const {
+        u32 h = hash32((u32)key) >> shift;
+        while (keys[h] != key) h = (h + 1) & mask;
+        return h;
+    }
+    __device__ __forceinline__ u32 cnt(u32 h) const { return vals[h]; }
+    __device__ __forceinline__ void set_cnt(u32 h, u32 v) { vals[h] = v; }
+    __device__ __forceinline__ u32 inc(u32 h) { return atomicAdd(&vals[h], 1u); }
+    __device__ __forceinline__ void set_bid(u32 h, i32 b) { bids[h] = b; }
+    __device__ __forceinline__ i32 bid(u32 h) const { return bids[h]; }
+    __device__ void reset(int, int) {}
+};
+
+// Dense counters over all labels in HBM with a touched list.  All accesses
+// are device-coherent (atomics or relaxed atomic loads/stores) so no stale
+// line in the CU's vector cache is ever read.
+struct DenseAcc {
+    u32 *c;
+    i32 *bids;
+    i32 *touch;
+    u32 *ntouch;
+    __device__ __forceinline__ void add(i32 key) {
+        u32 old = atomicAdd(&c[key], 1u);
+        if (old == 0) {
+            u32 t = atomicAdd(ntouch, 1u);
+            __hip_atomic_store(&touch[t], key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    __device__ __forceinline__ i64 entries() const {
+        return (i64)__hip_atomic_load(ntouch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __device__ __forceinline__ void entry(i64 i, i32 &key, u32 &cc) const {
+        key = __hip_atomic_load(&touch[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        cc = __hip_atomic_load(&c[key], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __device__ __forceinline__ u32 handle(i64 i) const {
+        return (u32)__hip_atomic_load(&touch[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __device__ __forceinline__ u32 find(i32 key) const { return (u32)key; }
+    __device__ __forceinline__ u32 cnt(u32 h) const {
+        return __hip_atomic_load(&c[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __device__ __forceinline__ void set_cnt(u32 h, u32 v) {
+        __hip_atomic_store(&c[h], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __device__ __forceinline__ u32 inc(u32 h) { return atomicAdd(&c[h], 1u); }
+    __device__ __forceinline__ void set_bid(u32 h, i32 b) {
+        __hip_atomic_store(&bids[h], b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __device__ __forceinline__ i32 bid(u32 h) const {
+        return __hip_atomic_load(&bids[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __device__ void reset(int tid, int nthreads) {
+        i64 nt = entries();
+        for (i64 i = tid; i < nt; i += nthreads) set_cnt(handle(i), 0u);
+        __syncthreads();
+        if (tid == 0) __hip_atomic_store(ntouch, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+    }
+};
+
+// ------------------------------------------------------------------ traversal
+
+struct ChunkSmem {
+    i32 *pre;    // [BLOCK] inclusive prefix of the chunk's prefix lengths
+    i64 *moff;   // [BLOCK] first entry of each mid's list
+    u64 *agg;    // [BLOCK] per-mid aggregate
+    i32 *wave;   // [BLOCK / WAVE]
+    u64 *red;    // [BLOCK / WAVE]
+    i64 *bcast;  // [1]
+};
+
+__device__ __forceinline__ u64 ld_coherent(const u64 *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ i64 ld_coherent(const i64 *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ u32 ld_coherent(const u32 *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Calls wedge(seg, jmid, last, pos) for every wedge of start s, where jmid is
+// the entry of mid in N_s, seg = jmid - chunk base, and pos the entry of last
+// in N_mid; chunk_end(cb) runs after each chunk of BLOCK mids, between
+// barriers.
+template <int BLOCK, class FW, class FC>
+__device__ __forceinline__ void for_each_wedge(const CountArgs &a, i32 s, const ChunkSmem &sm, FW wedge, FC chunk_end) {
+    const i64 jb = a.loff[s], je = a.loff[s + 1];
+    for (i64 cb = jb; cb < je; cb += BLOCK) {
+        i64 j = cb + threadIdx.x;
+        i32 pl = 0;
+        i64 moff = 0;
+        if (j < je) {
+            i32 mid = a.ladj[j];
+            pl = a.lpl[j];
+            if (a.alive && !a.alive[mid]) pl = 0;
+            moff = a.loff[mid];
+        }
+        i32 tot;
+        i32 incl = block_incl_scan_i32<BLOCK>(pl, sm.wave, tot);
+        sm.pre[threadIdx.x] = incl;
+        sm.moff[threadIdx.x] = moff;
+        __syncthreads();
+        for (i32 k = threadIdx.x; k < tot; k += BLOCK) {
+            int lo = 0, hi = BLOCK - 1;  // first seg with pre > k
+            while (lo < hi) {
+                int md = (lo + hi) >> 1;
+                if (sm.pre[md] > k) hi = md; else lo = md + 1;
+            }
+            i32 before = lo ? sm.pre[lo - 1] : 0;
+            i64 pos = sm.moff[lo] + (k - before);
+            i32 last = a.ladj[pos];
+            if (a.alive && !a.alive[last]) continue;
+            wedge(lo, cb + lo, last, pos);
+        }
+        __syncthreads();
+        chunk_end(cb);
+        __syncthreads();
+    }
+}
+
+// Everything done for one start: pass 1 (wedge counts), the per-bloom
+// epilogue, pass 2 (mid and edge contributions, twin pairs).
+template <int BLOCK, int MODE, class Acc>
+__device__ __forceinline__ void process_start(const CountArgs &a, i32 s, Acc &A, const ChunkSmem &sm, u64 &wedges) {
+    for_each_wedge<BLOCK>(a, s, sm, [&](int, i64, i32 last, i64) { A.add(last); ++wedges; }, [&](i64) {});
+
+    if (threadIdx.x == 0) sm.bcast[0] = A.entries();
+    __syncthreads();
+    const i64 ne = sm.bcast[0];
+    __syncthreads();
+    if (MODE & M_BE_FILL) {
+        const i64 bb = a.bbase[s], pb = a.pbase[s];
+        i64 carry_b = 0, carry_p = 0;
+        for (i64 base = 0; base < ne; base += BLOCK) {
+            i64 i = base + threadIdx.x;
+            i32 key = -1;
+            u32 cc = 0;
+            if (i < ne) A.entry(i, key, cc);
+            if (key < 0) cc = 0;
+            i32 f = cc >= 2 ? 1 : 0;
+            i32 tb, tp;
+            i32 ib = block_incl_scan_i32<BLOCK>(f, sm.wave, tb);
+            i32 ip = block_incl_scan_i32<BLOCK>(f ? (i32)cc : 0, sm.wave, tp);
+            if (i < ne && key >= 0) {
+                u32 h = A.handle(i);
+                if (f) {
+                    i64 bid = bb + carry_b + ib - 1;
+                    A.set_bid(h, (i32)bid);
+                    a.boff[bid] = pb + carry_p + ip - (i64)cc;
+                    a.bk[bid] = cc;
+                    A.set_cnt(h, 0u);  // becomes the fill cursor
+                } else {
+                    A.set_bid(h, -1);
+                }
+            }
+            carry_b += tb;
+            carry_p += tp;
+        }
+        __syncthreads();
+    } else {
+        u64 my_start = 0, my_blooms = 0, my_pairs = 0;
+        for (i64 i = threadIdx.x; i < ne; i += BLOCK) {
+            i32 key;
+            u32 c32;
+            A.entry(i, key, c32);
+            if (key < 0 || c32 < 2) continue;
+            u64 cc = c32;
+            u64 b = cc * (cc - 1) / 2;
+            if (MODE & M_VERTEX) {
+                my_start += b;
+                atomicAdd((unsigned long long *)&a.sup_label[key], (unsigned long long)b);
+            }
+            if (MODE & M_BE_SIZE) {
+                my_blooms += 1;
+                my_pairs += cc;
+            }
+        }
+        if (MODE & M_VERTEX) {
+            u64 t = block_sum_u64<BLOCK>(my_start, sm.red);
+            if (threadIdx.x == 0 && t) atomicAdd((unsigned long long *)&a.sup_label[s], (unsigned long long)t);
+        }
+        if (MODE & M_BE_SIZE) {
+            u64 tb = block_sum_u64<BLOCK>(my_blooms, sm.red);
+            u64 tp = block_sum_u64<BLOCK>(my_pairs, sm.red);
+            if (threadIdx.x == 0) {
+                a.bcnt[s] = (i64)tb;
+                a.pcnt[s] = (i64)tp;
+            }
+        }
+        __syncthreads();
+    }
+
+    if (MODE & (M_VERTEX | M_EDGE | M_BE_FILL)) {
+        sm.agg[threadIdx.x] = 0;
+        __syncthreads();
+        for_each_wedge<BLOCK>(a, s, sm,
+            [&](int seg, i64 jmid, i32 last, i64 pos) {
+                u32 h = A.find(last);
+                u64 cc;
+                if (MODE & M_BE_FILL) {
+                    i32 bid = A.bid(h);
+                    if (bid < 0) return;
+                    // written by this workgroup's epilogue: read coherently
+                    cc = ld_coherent(&a.bk[bid]);
+                    u32 slot = A.inc(h);
+                    i64 p = ld_coherent(&a.boff[bid]) + slot;
+                    a.bedge[2 * p] = a.leid[jmid];     // (start, mid)
+                    a.bedge[2 * p + 1] = a.leid[pos];  // (mid, last)
+                    a.pbloom[p] = bid;
+                } else {
+                    cc = A.cnt(h);
+                    if (cc < 2) return;
+                }
+                atomicAdd((unsigned long long *)&sm.agg[seg], (unsigned long long)(cc - 1));
+                if (MODE & (M_EDGE | M_BE_FILL))
+                    atomicAdd((unsigned long long *)&a.sup_edge[a.leid[pos]], (unsigned long long)(cc - 1));
+            },
+            [&](i64 cb) {
+                u64 g = sm.agg[threadIdx.x];
+                if (g) {
+                    i64 j = cb + threadIdx.x;
+                    if (MODE & M_VERTEX) atomicAdd((unsigned long long *)&a.sup_label[a.ladj[j]], (unsigned long long)g);
+                    if (MODE & (M_EDGE | M_BE_FILL))
+                        atomicAdd((unsigned long long *)&a.sup_edge[a.leid[j]], (unsigned long long)g);
+                    sm.agg[threadIdx.x] = 0;
+                }
+            });
+    }
+}
+
+// ------------------------------------------------------------------ kernels
+
+template <int BLOCK, int LOGCAP, int MODE>
+__global__ __launch_bounds__(BLOCK) void k_count_hash(CountArgs a) {
+    constexpr int CAP = 1 << LOGCAP;
+    __shared__ i32 s_keys[CAP];
+    __shared__ u32 s_vals[CAP];
+    __shared__ i32 s_bids[(MODE & M_BE_FILL) ? CAP : 1];
+    __shared__ i32 s_pre[BLOCK];
+    __shared__ i64 s_moff[BLOCK];
+    __shared__ u64 s_agg[BLOCK];
+    __shared__ i32 s_wave[BLOCK / WAVE];
+    __shared__ u64 s_red[BLOCK / WAVE];
+    __shared__ i32 s_item;
+    __shared__ i64 s_bcast[1];
+    ChunkSmem sm{s_pre, s_moff, s_agg, s_wave, s_red, s_bcast};
+    LdsAcc A;
+    A.keys = s_keys;
+    A.vals = s_vals;
+    A.bids = s_bids;
+    u64 wedges = 0;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = (i32)atomicAdd(a.next, 1u);
+        __syncthreads();
+        const i32 item = s_item;
+        __syncthreads();
+        if (item >= a.nstarts) break;
+        const i32 s = a.starts[item];
+        // capacity: a power of two at least twice the start's wedge count
+        const i64 ws = a.wsum[s];
+        int logcap = 6;
+        while ((i64(1) << logcap) < 2 * ws && logcap < LOGCAP) ++logcap;
+        A.init(logcap, threadIdx.x, BLOCK);
+        __syncthreads();
+        process_start<BLOCK, MODE>(a, s, A, sm, wedges);
+        __syncthreads();
+    }
+    if (wedges) atomicAdd((unsigned long long *)a.wedges, (unsigned long long)wedges);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_count_dense(CountArgs a) {
+    constexpr int BLOCK = 256;
+    __shared__ i32 s_pre[BLOCK];
+    __shared__ i64 s_moff[BLOCK];
+    __shared__ u64 s_agg[BLOCK];
+    __shared__ i32 s_wave[BLOCK / WAVE];
+    __shared__ u64 s_red[BLOCK / WAVE];
+    __shared__ i32 s_item;
+    __shared__ i64 s_bcast[1];
+    ChunkSmem sm{s_pre, s_moff, s_agg, s_wave, s_red, s_bcast};
+    DenseAcc A;
+    A.c = a.dcnt + (i64)blockIdx.x * a.n;
+    A.bids = a.dbid ? a.dbid + (i64)blockIdx.x * a.n : nullptr;
+    A.touch = a.dtouch + (i64)blockIdx.x * a.n;
+    A.ntouch = a.dntouch + blockIdx.x;
+    u64 wedges = 0;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = (i32)atomicAdd(a.next, 1u);
+        __syncthreads();
+        const i32 item = s_item;
+        __syncthreads();
+        if (item >= a.nstarts) break;
+        const i32 s = a.starts[item];
+        process_start<BLOCK, MODE>(a, s, A, sm, wedges);
+        __syncthreads();
+        A.reset(threadIdx.x, BLOCK);
+    }
+    if (wedges) atomicAdd((unsigned long long *)a.wedges, (unsigned long long)wedges);
+}
+
+// ------------------------------------------------------------------ binning
+
+constexpr i64 SMALL_W = 512, MEDIUM_W = 4096;
+
+__global__ void k_bin_starts(const i64 *wsum, const i32 *gid, const unsigned char *alive, i64 n, i32 *lists, u32 *counts) {
+    // lists: [3][n]; counts: [3]
+    for (i64 s = blockIdx.x * (i64)blockDim.x + threadIdx.x; s < n; s += (i64)gridDim.x * blockDim.x) {
+        i64 w = wsum[s];
+        if (w == 0) continue;
+        if (alive && !alive[s]) continue;
+        int b = w <= SMALL_W ? 0 : (w <= MEDIUM_W ? 1 : 2);
+        u32 p = atomicAdd(&counts[b], 1u);
+        lists[(i64)b * n + p] = (i32)s;
+    }
+}
+
+static int gridN(i64 n) {
+    i64 g = (n + 255) / 256;
+    return (int)(g < 1 ? 1 : (g > 16384 ? 16384 : g));
+}
+
+struct Bins {
+    i32 *lists;
+    u32 cnt[3];
+};
+
+static Bins bin_starts(Ctx &c, const DevGraph &G, const unsigned char *alive) {
+    Bins b;
+    b.lists = c.alloc<i32>(3 * G.n);
+    u32 *counts = c.alloc<u32>(4);
+    PBNG_HIP(hipMemsetAsync(counts, 0, 4 * sizeof(u32), c.stream));
+    if (G.n) {
+        hipLaunchKernelGGL(k_bin_starts, dim3(gridN(G.n)), dim3(256), 0, c.stream, (const i64 *)G.wsum, (const i32 *)G.gid,
+                           alive, G.n, b.lists, counts);
+        PBNG_LAUNCH_CHECK();
+    }
+    PBNG_HIP(hipMemcpyAsync(b.cnt, counts, 3 * sizeof(u32), hipMemcpyDeviceToHost, c.stream));
+    PBNG_HIP(hipStreamSynchronize(c.stream));
+    return b;
+}
+
+template <int MODE>
+static void launch_all(Ctx &c, const DevGraph &G, CountArgs a, const Bins &b) {
+    u32 *next = c.alloc<u32>(3);
+    PBNG_HIP(hipMemsetAsync(next, 0, 3 * sizeof(u32), c.stream));
+    // large starts first: they are the long tail
+    if (b.cnt[2]) {
+        int slots = (int)std::min<i64>(b.cnt[2], (i64)c.num_cu);
+        a.dcnt = c.alloc<u32>((i64)slots * G.n);
+        a.dtouch = c.alloc<i32>((i64)slots * G.n);
+        a.dbid = (MODE & M_BE_FILL) ? c.alloc<i32>((i64)slots * G.n) : nullptr;
+        a.dntouch = c.alloc<u32>(slots);
+        PBNG_HIP(hipMemsetAsync(a.dcnt, 0, sizeof(u32) * slots * G.n, c.stream));
+        PBNG_HIP(hipMemsetAsync(a.dntouch, 0, sizeof(u32) * slots, c.stream));
+        a.starts = b.lists + 2 * G.n;
+        a.nstarts = b.cnt[2];
+        a.next = next + 2;
+        hipLaunchKernelGGL(k_count_dense<MODE>, dim3(slots), dim3(256), 0, c.stream, a);
+        PBNG_LAUNCH_CHECK();
+    }
+    if (b.cnt[1]) {
+        a.starts = b.lists + G.n;
+        a.nstarts = b.cnt[1];
+        a.next = next + 1;
+        int grid = (int)std::min<i64>(b.cnt[1], (i64)c.num_cu * 2);
+        hipLaunchKernelGGL((k_count_hash<256, 13, MODE>), dim3(grid), dim3(256), 0, c.stream, a);
+        PBNG_LAUNCH_CHECK();
+    }
+    if (b.cnt[0]) {
+        a.starts = b.lists;
+        a.nstarts = b.cnt[0];
+        a.next = next;
+        int grid = (int)std::min<i64>(b.cnt[0], (i64)c.num_cu * 16);
+        hipLaunchKernelGGL((k_count_hash<64, 10, MODE>), dim3(grid), dim3(64), 0, c.stream, a);
+        PBNG_LAUNCH_CHECK();
+    }
+}
+
+static CountArgs base_args(const DevGraph &G) {
+    CountArgs a{};
+    a.loff = G.loff;
+    a.ladj = G.ladj;
+    a.leid = G.leid;
+    a.lpl = G.lpl;
+    a.wsum = G.wsum;
+    a.n = G.n;
+    return a;
+}
+
+u64 count_pass(Ctx &c, const DevGraph &G, u64 *sup_label, u64 *sup_edge, const unsigned char *alive) {
+    CountArgs a = base_args(G);
+    a.alive = alive;
+    a.sup_label = sup_label;
+    a.sup_edge = sup_edge;
+    a.wedges = c.alloc<u64>(1);
+    PBNG_HIP(hipMemsetAsync(a.wedges, 0, sizeof(u64), c.stream));
+    if (sup_label) PBNG_HIP(hipMemsetAsync(sup_label, 0, sizeof(u64) * (G.n ? G.n : 1), c.stream));
+    if (sup_edge) PBNG_HIP(hipMemsetAsync(sup_edge, 0, sizeof(u64) * (G.m ? G.m : 1), c.stream));
+    Bins b = bin_starts(c, G, alive);
+    if (sup_label && sup_edge) launch_all<M_VERTEX | M_EDGE>(c, G, a, b);
+    else if (sup_label) launch_all<M_VERTEX>(c, G, a, b);
+    else if (sup_edge) launch_all<M_EDGE>(c, G, a, b);
+    return read_scalar<u64>(c, a.wedges);
+}
+
+void count_butterflies(Ctx &c, const DevGraph &G, const CountOut &out, const pbng_opts &) {
+    u64 w = count_pass(c, G, out.sup_label, out.sup_edge, nullptr);
+    c.stats.wedges_count += w;
+    c.stats.wedges += w;
+}
+
+// ------------------------------------------------------------------ gather
+
+__global__ void k_gather_side(const u64 *sup_label, const i32 *label, i64 off, i64 cnt, u64 *out) {
+    for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < cnt; i += (i64)gridDim.x * blockDim.x)
+        out[i] = sup_label[label[off + i]];
+}
+
+void gather_side(Ctx &c, const DevGraph &G, const u64 *sup_label, int side, u64 *out) {
+    i64 off = side == 0 ? 0 : G.n_u;
+    i64 cnt = side == 0 ? G.n_u : G.n_v;
+    if (!cnt) return;
+    hipLaunchKernelGGL(k_gather_side, dim3(gridN(cnt)), dim3(256), 0, c.stream, sup_label, (const i32 *)G.label, off, cnt, out);
+    PBNG_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------------ BE-Index
+
+__global__ void k_edge_link_count(const i32 *bedge, i64 npairs, u32 *ecnt) {
+    for (i64 p = blockIdx.x * (i64)blockDim.x + threadIdx.x; p < npairs; p += (i64)gridDim.x * blockDim.x) {
+        atomicAdd(&ecnt[bedge[2 * p]], 1u);
+        atomicAdd(&ecnt[bedge[2 * p + 1]], 1u);
+    }
+}
+
+__global__ void k_u32_to_i64(const u32 *a, i64 n, i64 *b) {
+    for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) b[i] = a[i];
+}
+
+__global__ void k_edge_link_fill(const i32 *bedge, const i32 *pbloom, i64 npairs, i64 *cursor, i32 *ebloom, i32 *etwin) {
+    for (i64 p = blockIdx.x * (i64)blockDim.x + threadIdx.x; p < npairs; p += (i64)gridDim.x * blockDim.x) {
+        i32 e1 = bedge[2 * p], e2 = bedge[2 * p + 1], b = pbloom[p];
+        i64 q1 = atomicAdd((unsigned long long *)&cursor[e1], 1ull);
+        ebloom[q1] = b;
+        etwin[q1] = e2;
+        i64 q2 = atomicAdd((unsigned long long *)&cursor[e2], 1ull);
+        ebloom[q2] = b;
+        etwin[q2] = e1;
+    }
+}
+
+void build_be_index(Ctx &c, const DevGraph &G, BEIndex &I, u64 *sup_edge) {
+    const i64 n = G.n, m = G.m;
+    CountArgs a = base_args(G);
+    a.wedges = c.alloc<u64>(1);
+    PBNG_HIP(hipMemsetAsync(a.wedges, 0, sizeof(u64), c.stream));
+    Bins b = bin_starts(c, G, nullptr);
+    // sizes
+    a.bcnt = c.alloc<i64>(n);
+    a.pcnt = c.alloc<i64>(n);
+    PBNG_HIP(hipMemsetAsync(a.bcnt, 0, sizeof(i64) * (n ? n : 1), c.stream));
+    PBNG_HIP(hipMemsetAsync(a.pcnt, 0, sizeof(i64) * (n ? n : 1), c.stream));
+    launch_all<M_BE_SIZE>(c, G, a, b);
+    i64 *bbase = c.alloc<i64>(n + 1);
+    i64 *pbase = c.alloc<i64>(n + 1);
+    exclusive_scan<i64>(c, a.bcnt, bbase, n);
+    exclusive_scan<i64>(c, a.pcnt, pbase, n);
+    I.nblooms = read_scalar<i64>(c, bbase + n);
+    I.npairs = read_scalar<i64>(c, pbase + n);
+    if (I.nblooms >= (i64(1) << 31) || 2 * I.npairs >= (i64(1) << 40))
+        throw Error(PBNG_E_OVERFLOW, "BE-Index larger than the index widths");
+    I.boff = c.alloc<i64>(I.nblooms + 1);
+    I.bk = c.alloc<u32>(I.nblooms);
+    I.bedge = c.alloc<i32>(2 * I.npairs);
+    i32 *pbloom = c.alloc<i32>(I.npairs);
+    // fill (also the per-edge supports)
+    a.bbase = bbase;
+    a.pbase = pbase;
+    a.boff = I.boff;
+    a.bk = I.bk;
+    a.bedge = I.bedge;
+    a.pbloom = pbloom;
+    a.sup_edge = sup_edge;
+    PBNG_HIP(hipMemsetAsync(sup_edge, 0, sizeof(u64) * (m ? m : 1), c.stream));
+    launch_all<M_BE_FILL>(c, G, a, b);
+    PBNG_HIP(hipMemcpyAsync(I.boff + I.nblooms, &I.npairs, sizeof(i64), hipMemcpyHostToDevice, c.stream));
+    // edge-major links
+    u32 *ecnt = c.alloc<u32>(m);
+    i64 *ecnt64 = c.alloc<i64>(m);
+    PBNG_HIP(hipMemsetAsync(ecnt, 0, sizeof(u32) * (m ? m : 1), c.stream));
+    if (I.npairs) {
+        hipLaunchKernelGGL(k_edge_link_count, dim3(gridN(I.npairs)), dim3(256), 0, c.stream, (const i32 *)I.bedge, I.npairs, ecnt);
+        PBNG_LAUNCH_CHECK();
+    }
+    if (m) {
+        hipLaunchKernelGGL(k_u32_to_i64, dim3(gridN(m)), dim3(256), 0, c.stream, (const u32 *)ecnt, m, ecnt64);
+        PBNG_LAUNCH_CHECK();
+    }
+    I.eoff = c.alloc<i64>(m + 1);
+    exclusive_scan<i64>(c, ecnt64, I.eoff, m);
+    i64 *cursor = c.alloc<i64>(m);
+    if (m) PBNG_HIP(hipMemcpyAsync(cursor, I.eoff, sizeof(i64) * m, hipMemcpyDeviceToDevice, c.stream));
+    I.ebloom = c.alloc<i32>(2 * I.npairs);
+    I.etwin = c.alloc<i32>(2 * I.npairs);
+    if (I.npairs) {
+        hipLaunchKernelGGL(k_edge_link_fill, dim3(gridN(I.npairs)), dim3(256), 0, c.stream, (const i32 *)I.bedge,
+                           (const i32 *)pbloom, I.npairs, cursor, I.ebloom, I.etwin);
+        PBNG_LAUNCH_CHECK();
+    }
+    u64 w = read_scalar<u64>(c, a.wedges);
+    c.stats.wedges_count += w;
+    c.stats.wedges += w;
+    c.stats.blooms = I.nblooms;
+    c.stats.bloom_pairs = I.npairs;
+}
+
+}  // namespace pbng

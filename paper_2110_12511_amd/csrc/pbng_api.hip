@@ -1,0 +1,224 @@
+// C ABI of the library (include/pbng.h): argument checks, host/device
+// marshalling of the caller's graph, phase timing, error translation.
+#include <chrono>
+#include <cstring>
+
+#include "pbng_internal.h"
+
+struct pbng_ctx {
+    pbng::Ctx c;
+};
+
+namespace pbng {
+
+namespace {
+
+struct CallScope {
+    // Returns the arena to its free list when a call ends, however it ends.
+    Ctx &c;
+    explicit CallScope(Ctx &cc) : c(cc) { c.stats = pbng_stats{}; }
+    ~CallScope() {
+        (void)hipStreamSynchronize(c.stream);
+        c.arena.release_all();
+    }
+};
+
+int fail(Ctx &c, int code, const std::string &msg) {
+    c.last_error = msg;
+    return code;
+}
+
+int check_csr(const pbng_csr *g) {
+    if (!g) return PBNG_E_ARG;
+    if (g->n_u < 0 || g->n_v < 0 || g->m < 0) return PBNG_E_ARG;
+    if (!g->row_ptr) return PBNG_E_ARG;
+    if (g->m > 0 && !g->col_idx) return PBNG_E_ARG;
+    // label pair keys need n^2 < 2^64 and entry indices need 2m < 2^31
+    if (g->n_u + g->n_v >= (int64_t(1) << 31) - 1) return PBNG_E_OVERFLOW;
+    if (g->m >= (int64_t(1) << 30)) return PBNG_E_OVERFLOW;
+    return 0;
+}
+
+// Device view of the caller's graph (copied in when it lives on the host).
+pbng_csr device_graph(Ctx &c, const pbng_csr &g) {
+    if (g.on_device) return g;
+    pbng_csr d = g;
+    i64 *rp = c.alloc<i64>(g.n_u + 1);
+    i32 *ci = c.alloc<i32>(g.m);
+    PBNG_HIP(hipMemcpyAsync(rp, g.row_ptr, sizeof(i64) * (g.n_u + 1), hipMemcpyHostToDevice, c.stream));
+    if (g.m) PBNG_HIP(hipMemcpyAsync(ci, g.col_idx, sizeof(i32) * g.m, hipMemcpyHostToDevice, c.stream));
+    d.row_ptr = rp;
+    d.col_idx = ci;
+    d.on_device = 1;
+    return d;
+}
+
+// Output buffer on the device; copied back to the host when the caller's
+// graph is on the host.
+struct OutBuf {
+    Ctx &c;
+    u64 *user;
+    u64 *dev;
+    i64 n;
+    bool host;
+    OutBuf(Ctx &cc, u64 *u, i64 nn, bool h) : c(cc), user(u), dev(nullptr), n(nn), host(h) {
+        dev = host ? c.alloc<u64>(n) : u;
+    }
+    void finish() {
+        if (host && n) PBNG_HIP(hipMemcpyAsync(user, dev, sizeof(u64) * n, hipMemcpyDeviceToHost, c.stream));
+        PBNG_HIP(hipStreamSynchronize(c.stream));
+    }
+};
+
+pbng_opts default_opts(const pbng_opts *o) {
+    pbng_opts d{};
+    if (o) d = *o;
+    return d;
+}
+
+double ms_since(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+template <class F>
+int guarded(Ctx &c, F f) {
+    try {
+        f();
+        return PBNG_OK;
+    } catch (const Error &e) {
+        return fail(c, e.code, e.what());
+    } catch (const std::bad_alloc &) {
+        return fail(c, PBNG_E_NOMEM, "host allocation failed");
+    } catch (const std::exception &e) {
+        return fail(c, PBNG_E_DEVICE, e.what());
+    } catch (...) {
+        return fail(c, PBNG_E_DEVICE, "unknown error");
+    }
+}
+
+}  // namespace
+}  // namespace pbng
+
+using namespace pbng;
+
+extern "C" {
+
+int pbng_create(pbng_ctx **out, void *stream) {
+    if (!out) return PBNG_E_ARG;
+    *out = nullptr;
+    pbng_ctx *x = nullptr;
+    try {
+        x = new pbng_ctx();
+    } catch (...) {
+        return PBNG_E_NOMEM;
+    }
+    x->c.stream = static_cast<hipStream_t>(stream);
+    if (hipGetDevice(&x->c.device) != hipSuccess) {
+        delete x;
+        return PBNG_E_DEVICE;
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, x->c.device) == hipSuccess && prop.multiProcessorCount > 0)
+        x->c.num_cu = prop.multiProcessorCount;
+    *out = x;
+    return PBNG_OK;
+}
+
+void pbng_destroy(pbng_ctx *x) {
+    if (!x) return;
+    (void)hipStreamSynchronize(x->c.stream);
+    x->c.arena.destroy();
+    delete x;
+}
+
+const char *pbng_last_error(pbng_ctx *x) { return x ? x->c.last_error.c_str() : "null context"; }
+
+int pbng_last_stats(pbng_ctx *x, pbng_stats *out) {
+    if (!x || !out) return PBNG_E_ARG;
+    *out = x->c.stats;
+    return PBNG_OK;
+}
+
+int pbng_count(pbng_ctx *x, const pbng_csr *g, pbng_count_kind kind, const pbng_opts *opts, uint64_t *out) {
+    if (!x) return PBNG_E_ARG;
+    Ctx &c = x->c;
+    int rc = check_csr(g);
+    if (rc) return fail(c, rc, "bad graph arguments");
+    if (kind != PBNG_COUNT_VERTEX_U && kind != PBNG_COUNT_VERTEX_V && kind != PBNG_COUNT_EDGE)
+        return fail(c, PBNG_E_ARG, "bad count kind");
+    i64 nout = kind == PBNG_COUNT_VERTEX_U ? g->n_u : (kind == PBNG_COUNT_VERTEX_V ? g->n_v : g->m);
+    if (nout > 0 && !out) return fail(c, PBNG_E_ARG, "null output");
+    CallScope scope(c);
+    pbng_opts o = default_opts(opts);
+    return guarded(c, [&] {
+        auto t0 = std::chrono::steady_clock::now();
+        pbng_csr dg = device_graph(c, *g);
+        OutBuf ob(c, out, nout, !g->on_device);
+        DevGraph G;
+        build_graph(c, dg, G);
+        PBNG_HIP(hipStreamSynchronize(c.stream));
+        c.stats.ms_prep = ms_since(t0);
+        auto t1 = std::chrono::steady_clock::now();
+        if (kind == PBNG_COUNT_EDGE) {
+            CountOut co;
+            co.sup_edge = ob.dev;
+            count_butterflies(c, G, co, o);
+        } else {
+            CountOut co;
+            co.sup_label = c.alloc<u64>(G.n);
+            count_butterflies(c, G, co, o);
+            gather_side(c, G, co.sup_label, kind == PBNG_COUNT_VERTEX_U ? 0 : 1, ob.dev);
+        }
+        ob.finish();
+        c.stats.ms_count = ms_since(t1);
+        c.stats.ms_total = ms_since(t0);
+    });
+}
+
+int pbng_tip(pbng_ctx *x, const pbng_csr *g, pbng_side side, const pbng_opts *opts, uint64_t *tip_out) {
+    if (!x) return PBNG_E_ARG;
+    Ctx &c = x->c;
+    int rc = check_csr(g);
+    if (rc) return fail(c, rc, "bad graph arguments");
+    if (side != PBNG_SIDE_U && side != PBNG_SIDE_V) return fail(c, PBNG_E_ARG, "bad side");
+    i64 nout = side == PBNG_SIDE_U ? g->n_u : g->n_v;
+    if (nout > 0 && !tip_out) return fail(c, PBNG_E_ARG, "null output");
+    CallScope scope(c);
+    pbng_opts o = default_opts(opts);
+    return guarded(c, [&] {
+        auto t0 = std::chrono::steady_clock::now();
+        pbng_csr dg = device_graph(c, *g);
+        OutBuf ob(c, tip_out, nout, !g->on_device);
+        DevGraph G;
+        build_graph(c, dg, G);
+        PBNG_HIP(hipStreamSynchronize(c.stream));
+        c.stats.ms_prep = ms_since(t0);
+        tip_decompose(c, G, side, o, ob.dev);
+        ob.finish();
+        c.stats.ms_total = ms_since(t0);
+    });
+}
+
+int pbng_wing(pbng_ctx *x, const pbng_csr *g, const pbng_opts *opts, uint64_t *wing_out) {
+    if (!x) return PBNG_E_ARG;
+    Ctx &c = x->c;
+    int rc = check_csr(g);
+    if (rc) return fail(c, rc, "bad graph arguments");
+    if (g->m > 0 && !wing_out) return fail(c, PBNG_E_ARG, "null output");
+    CallScope scope(c);
+    pbng_opts o = default_opts(opts);
+    return guarded(c, [&] {
+        auto t0 = std::chrono::steady_clock::now();
+        pbng_csr dg = device_graph(c, *g);
+        OutBuf ob(c, wing_out, g->m, !g->on_device);
+        DevGraph G;
+        build_graph(c, dg, G);
+        PBNG_HIP(hipStreamSynchronize(c.stream));
+        c.stats.ms_prep = ms_since(t0);
+        wing_decompose(c, G, o, ob.dev);
+        ob.finish();
+        c.stats.ms_total = ms_since(t0);
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,134 @@
+// Internal declarations of the gfx950 butterfly-peeling library.
+// Host orchestration is C++17 over the HIP runtime; kernels are HIP for
+// CDNA4 (wave64).  Nothing here is exported: the C ABI is in include/pbng.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <map>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/pbng.h"
+
+namespace pbng {
+
+typedef uint64_t u64;
+typedef int64_t i64;
+typedef uint32_t u32;
+typedef int32_t i32;
+
+constexpr int WAVE = 64;
+
+// Error carried to the C ABI boundary, where it becomes a return code.
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+#define PBNG_HIP(call)                                                              \
+    do {                                                                            \
+        hipError_t e_ = (call);                                                     \
+        if (e_ != hipSuccess)                                                       \
+            throw ::pbng::Error(e_ == hipErrorOutOfMemory ? PBNG_E_NOMEM : PBNG_E_DEVICE, \
+                                std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define PBNG_LAUNCH_CHECK() PBNG_HIP(hipGetLastError())
+
+// Device memory cache owned by a context: blocks are reused across calls and
+// freed by pbng_destroy.  take() returns a block of at least `bytes`.
+struct Arena {
+    std::multimap<size_t, void *> free_blocks;
+    std::vector<std::pair<void *, size_t>> in_use;
+    size_t bytes_held = 0;
+    void *take(size_t bytes);
+    void release_all();  // back to the free list (end of a call)
+    void destroy();      // hipFree everything
+};
+
+struct Ctx {
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int num_cu = 256;
+    Arena arena;
+    std::string last_error;
+    pbng_stats stats{};
+    // pinned host staging for small device->host status reads
+    void *host_stage = nullptr;
+    template <class T>
+    T *alloc(size_t n) {
+        return static_cast<T *>(arena.take((n ? n : 1) * sizeof(T)));
+    }
+};
+
+// Graph in device memory after preprocessing (Algorithm 1, priority
+// assignment and sorted adjacency).  Global vertex ids: U = [0, n_u),
+// V = [n_u, n_u + n_v).  A label is the vertex's position in the order of
+// decreasing degree (ties by increasing global id).
+struct DevGraph {
+    i64 n_u = 0, n_v = 0, n = 0, m = 0;
+    const i64 *urow = nullptr;  // U-side CSR (caller's, on device)
+    const i32 *ucol = nullptr;
+    i64 *vrow = nullptr;        // V-side CSR: U ids, and edge ids
+    i32 *vadj = nullptr;
+    i32 *veid = nullptr;
+    i32 *label = nullptr;       // [n] global id -> label
+    i32 *gid = nullptr;         // [n] label -> global id
+    i64 *loff = nullptr;        // [n+1] label CSR offsets
+    i32 *ladj = nullptr;        // [2m] neighbour labels, ascending per row
+    i32 *leid = nullptr;        // [2m] edge id of each entry
+    i32 *lpl = nullptr;         // [2m] wedge-prefix length of (row, entry), see prep
+    i64 *wsum = nullptr;        // [n+1] exclusive prefix of lpl per row (wedges per start)
+};
+
+// ---- primitives (prims.hip) ----
+template <class T>
+void exclusive_scan(Ctx &c, const T *in, T *out, i64 n);  // out[0..n], out[n] = total
+void radix_sort_u64(Ctx &c, u64 *keys, i32 *vals, i64 n, int bits, u64 **keys_out, i32 **vals_out);
+void iota_i32(Ctx &c, i32 *p, i64 n);
+template <class T>
+void fill(Ctx &c, T *p, T v, i64 n);
+u64 reduce_sum_u64(Ctx &c, const u64 *p, i64 n);  // synchronous
+template <class T>
+T read_scalar(Ctx &c, const T *dev);               // synchronous
+
+// ---- graph preprocessing (prep.hip) ----
+void build_graph(Ctx &c, const pbng_csr &g, DevGraph &G);
+
+// ---- counting (count.hip) ----
+struct CountOut {
+    u64 *sup_label = nullptr;  // [n] per-vertex butterflies by label (or null)
+    u64 *sup_edge = nullptr;   // [m] per-edge butterflies (or null)
+};
+void count_butterflies(Ctx &c, const DevGraph &G, const CountOut &out, const pbng_opts &o);
+// Per-vertex counts of the rows of an arbitrary "peeled side" view are
+// produced by count_butterflies on the full graph and gathered by label.
+void gather_side(Ctx &c, const DevGraph &G, const u64 *sup_label, int side, u64 *out);
+
+// BE-Index (Section 2.3) built from the counting traversal.
+struct BEIndex {
+    i64 nblooms = 0, npairs = 0;
+    i64 *boff = nullptr;   // [nblooms+1] pair offsets per bloom
+    u32 *bk = nullptr;     // [nblooms] live pairs (bloom number k_B)
+    i32 *bedge = nullptr;  // [2*npairs] edge ids, pair p at 2p, 2p+1 (twins)
+    i64 *eoff = nullptr;   // [m+1] link offsets per edge
+    i32 *ebloom = nullptr; // [2*npairs] bloom of each link
+    i32 *etwin = nullptr;  // [2*npairs] twin edge of each link
+};
+void build_be_index(Ctx &c, const DevGraph &G, BEIndex &I, u64 *sup_edge);
+
+// ---- decompositions ----
+void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 *theta_dev);
+void wing_decompose(Ctx &c, const DevGraph &G, const pbng_opts &o, u64 *theta_dev);
+
+// ---- range selection (select.hip) ----
+// Smallest s with sum{w_l : active_l, key_l <= s} >= target; if the total is
+// below target, the largest active key.  Result written to *s_out (device).
+void weighted_select(Ctx &c, const u64 *key, const u64 *w, const unsigned char *state,
+                     unsigned char alive_code, i64 n, const u64 *target_dev, u64 *s_out,
+                     u64 *work_at_s_out);
+
+}  // namespace pbng

@@ -18,3 +18,12 @@ def oracle_mod():
     import oracle
 
     return oracle
+
+
+@pytest.fixture(scope="session")
+def ctx():
+    import paper_2110_12511_amd as pb
+
+    c = pb.Context()
+    yield c
+    c.close()

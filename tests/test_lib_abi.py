@@ -1,0 +1,38 @@
+"""CPU-side checks of the built library: it loads and exports every symbol
+declared in include/pbng.h, and the Python binding mirrors the ABI structs."""
+import ctypes
+import os
+import re
+
+import paper_2110_12511_amd as pb
+from paper_2110_12511_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "pbng.h")).read()
+    return sorted(set(re.findall(r"\b(pbng_[a-z_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol():
+    lib = pb.load()
+    names = _declared()
+    assert "pbng_count" in names and "pbng_tip" in names and "pbng_wing" in names
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_struct_layouts():
+    # pbng_csr: 3 x int64 + 2 pointers + int32 (+pad); pbng_opts: 8 x int32
+    assert ctypes.sizeof(binding.Csr) == 48
+    assert ctypes.sizeof(binding.Opts) == 32
+    assert ctypes.sizeof(binding.Stats) == 6 * 8 + 10 * 8 + 2 * 4 + 3 * 8
+
+
+def test_null_context_rejected():
+    lib = pb.load()
+    assert lib.pbng_count(None, None, 0, None, None) == -1
+    assert lib.pbng_tip(None, None, 0, None, None) == -1
+    assert lib.pbng_wing(None, None, None, None) == -1
+    assert lib.pbng_last_stats(None, None) == -1
