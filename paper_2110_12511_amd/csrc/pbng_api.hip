@@ -128,6 +128,7 @@ void pbng_destroy(pbng_ctx *x) {
     if (!x) return;
     (void)hipStreamSynchronize(x->c.stream);
     x->c.arena.destroy();
+    if (x->c.sel_scratch) (void)hipFree(x->c.sel_scratch);
     delete x;
 }
 

@@ -56,8 +56,8 @@ struct Ctx {
     Arena arena;
     std::string last_error;
     pbng_stats stats{};
-    // pinned host staging for small device->host status reads
-    void *host_stage = nullptr;
+    // device scratch of the range selection, kept for the context's life
+    void *sel_scratch = nullptr;
     template <class T>
     T *alloc(size_t n) {
         return static_cast<T *>(arena.take((n ? n : 1) * sizeof(T)));
@@ -127,8 +127,17 @@ void wing_decompose(Ctx &c, const DevGraph &G, const pbng_opts &o, u64 *theta_de
 // ---- range selection (select.hip) ----
 // Smallest s with sum{w_l : active_l, key_l <= s} >= target; if the total is
 // below target, the largest active key.  Result written to *s_out (device).
+// The target is *target_dev, or, when scale_dev is given, the plain rule's
+// scale * (alive work) / parts_left computed on the device.
 void weighted_select(Ctx &c, const u64 *key, const u64 *w, const unsigned char *state,
-                     unsigned char alive_code, i64 n, const u64 *target_dev, u64 *s_out,
-                     u64 *work_at_s_out);
+                     unsigned char alive_code, i64 n, const u64 *target_dev, const double *scale_dev,
+                     int parts_left, u64 *s_out, u64 *work_at_s_out);
+
+// Counting pass with an optional alive filter by label (recounts).
+// Returns the wedges walked.  sup_label / sup_edge are overwritten.
+u64 count_pass(Ctx &c, const DevGraph &G, u64 *sup_label, u64 *sup_edge, const unsigned char *alive_label);
+
+int bits_for(u64 maxval);
+int grid_1d(i64 n, int block = 256, int cap = 16384);
 
 }  // namespace pbng

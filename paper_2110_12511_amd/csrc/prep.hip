@@ -125,11 +125,6 @@ static int gridN(i64 n) {
     return (int)(g < 1 ? 1 : (g > 16384 ? 16384 : g));
 }
 
-static int bits_for(u64 maxval) {
-    int b = 0;
-    while (b < 64 && (maxval >> b) != 0) ++b;
-    return (b + 7) / 8 * 8;
-}
 
 void build_graph(Ctx &c, const pbng_csr &g, DevGraph &G) {
     G.n_u = g.n_u;

@@ -60,6 +60,20 @@ __global__ void k_iota(i32 *p, i64 n) {
     for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) p[i] = (i32)i;
 }
 
+// Radix-sort width: bits needed for maxval, rounded up to whole bytes.
+int bits_for(u64 maxval) {
+    int b = 0;
+    while (b < 64 && (maxval >> b) != 0) ++b;
+    return (b + 7) / 8 * 8;
+}
+
+int grid_1d(i64 n, int block, int cap) {
+    i64 g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
 static int grid_for(i64 n, int block = 256, int cap = 8192) {
     i64 g = (n + block - 1) / block;
     if (g < 1) g = 1;

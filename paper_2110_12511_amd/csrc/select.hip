@@ -1,0 +1,159 @@
+// Range determination of the coarse-grained phase (Algorithm 4, find_range;
+// Section 3.1.3).  Given the alive entities' supports (u64 keys) and work
+// estimates, find the smallest support value s whose cumulative work
+// sum{w_l : alive l, key_l <= s} reaches the target; when the alive work
+// total is below the target, s is the largest alive support.
+//
+// Supports reach ~1e12 for tip decomposition, so bins per support value are
+// not possible; the selection descends the key's bits 8 at a time (an
+// MSB-first radix select with work-weighted 256-bin histograms).
+#include "pbng_internal.h"
+
+namespace pbng {
+
+struct SelState {
+    u64 total;     // alive work
+    u64 maxkey;    // largest alive key
+    u64 prefix;    // bits decided so far
+    u64 rem;       // target still to cover inside the current prefix bucket
+    u64 target;
+    u64 result;    // s
+    u64 work;      // cumulative work at s
+    u64 done;      // 1 when the total was below target (result = maxkey)
+};
+
+__global__ __launch_bounds__(256) void k_sel_total(const u64 *key, const u64 *w, const unsigned char *state,
+                                                  unsigned char alive, i64 n, SelState *st) {
+    u64 t = 0, mx = 0;
+    for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) {
+        if (state[i] != alive) continue;
+        t += w[i];
+        u64 k = key[i];
+        mx = k > mx ? k : mx;
+    }
+    for (int d = WAVE / 2; d > 0; d >>= 1) {
+        t += __shfl_down(t, d, WAVE);
+        u64 o = __shfl_down(mx, d, WAVE);
+        mx = o > mx ? o : mx;
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd((unsigned long long *)&st->total, (unsigned long long)t);
+        atomicMax((unsigned long long *)&st->maxkey, (unsigned long long)mx);
+    }
+}
+
+// Target of the plain rule (Section 3.1.3): the alive work spread over the
+// partitions still to create, times the scaling factor of the previous
+// partition (ratio of its initial to its final work estimate).
+__global__ void k_sel_init(SelState *st, const u64 *target, const double *scale, int parts_left) {
+    u64 tg;
+    if (scale) {
+        double t = (double)st->total / (double)(parts_left > 0 ? parts_left : 1) * scale[0];
+        tg = t >= 1.8e19 ? ~0ull : (u64)t;
+    } else {
+        tg = *target;
+    }
+    if (tg == 0) tg = 1;
+    st->target = tg;
+    st->prefix = 0;
+    st->rem = tg;
+    if (st->total < tg) {
+        st->done = 1;
+        st->result = st->maxkey;
+        st->work = st->total;
+    } else {
+        st->done = 0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_sel_hist(const u64 *key, const u64 *w, const unsigned char *state,
+                                                 unsigned char alive, i64 n, int shift, const SelState *st, u64 *hist) {
+    __shared__ u64 h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    if (!st->done) {
+        const u64 pre = st->prefix;
+        const int hs = shift + 8;
+        for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) {
+            if (state[i] != alive) continue;
+            u64 k = key[i];
+            if (hs < 64 && (k >> hs) != (pre >> hs)) continue;
+            atomicAdd((unsigned long long *)&h[(k >> shift) & 255], (unsigned long long)w[i]);
+        }
+    }
+    __syncthreads();
+    if (h[threadIdx.x]) atomicAdd((unsigned long long *)&hist[threadIdx.x], (unsigned long long)h[threadIdx.x]);
+}
+
+__global__ void k_sel_pick(SelState *st, int shift, u64 *hist) {
+    // one thread: the smallest digit whose cumulative weight covers the
+    // remaining target; clears the histogram for the next level
+    const bool active = !st->done;
+    u64 rem = st->rem, cum = 0;
+    int pick = -1;
+    for (int d = 0; d < 256; ++d) {
+        u64 h = hist[d];
+        if (active && pick < 0) {
+            if (h > 0 && cum + h >= rem) {
+                pick = d;
+                st->rem = rem - cum;
+            } else {
+                cum += h;
+            }
+        }
+        hist[d] = 0;
+    }
+    if (active) st->prefix |= (u64)(pick < 0 ? 255 : pick) << shift;
+}
+
+__global__ __launch_bounds__(256) void k_sel_work(const u64 *key, const u64 *w, const unsigned char *state,
+                                                 unsigned char alive, i64 n, SelState *st) {
+    if (st->done) return;
+    const u64 s = st->prefix;
+    u64 t = 0;
+    for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x)
+        if (state[i] == alive && key[i] <= s) t += w[i];
+    for (int d = WAVE / 2; d > 0; d >>= 1) t += __shfl_down(t, d, WAVE);
+    if ((threadIdx.x & 63) == 0) atomicAdd((unsigned long long *)&st->work, (unsigned long long)t);
+}
+
+__global__ void k_sel_finish(SelState *st, u64 *s_out, u64 *work_out) {
+    if (!st->done) st->result = st->prefix;
+    *s_out = st->result;
+    if (work_out) *work_out = st->work;
+}
+
+static int grid_sel(i64 n) {
+    i64 g = (n + 255) / 256;
+    return (int)(g < 1 ? 1 : (g > 2048 ? 2048 : g));
+}
+
+// All launches are asynchronous on the context stream; results stay on the
+// device.  The number of 8-bit levels is fixed at 8 (full u64 keys) unless
+// `key_bits` narrows it.
+void weighted_select(Ctx &c, const u64 *key, const u64 *w, const unsigned char *state, unsigned char alive, i64 n,
+                     const u64 *target_dev, const double *scale_dev, int parts_left, u64 *s_out,
+                     u64 *work_at_s_out) {
+    if (!c.sel_scratch) PBNG_HIP(hipMalloc(&c.sel_scratch, sizeof(SelState) + 256 * sizeof(u64)));
+    SelState *st = static_cast<SelState *>(c.sel_scratch);
+    u64 *hist = reinterpret_cast<u64 *>(st + 1);
+    PBNG_HIP(hipMemsetAsync(st, 0, sizeof(SelState), c.stream));
+    PBNG_HIP(hipMemsetAsync(hist, 0, 256 * sizeof(u64), c.stream));
+    hipLaunchKernelGGL(k_sel_total, dim3(grid_sel(n)), dim3(256), 0, c.stream, key, w, state, alive, n, st);
+    PBNG_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(1), 0, c.stream, st, target_dev, scale_dev, parts_left);
+    PBNG_LAUNCH_CHECK();
+    for (int shift = 56; shift >= 0; shift -= 8) {
+        hipLaunchKernelGGL(k_sel_hist, dim3(grid_sel(n)), dim3(256), 0, c.stream, key, w, state, alive, n, shift,
+                           (const SelState *)st, hist);
+        PBNG_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_sel_pick, dim3(1), dim3(1), 0, c.stream, st, shift, hist);
+        PBNG_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(k_sel_work, dim3(grid_sel(n)), dim3(256), 0, c.stream, key, w, state, alive, n, st);
+    PBNG_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_sel_finish, dim3(1), dim3(1), 0, c.stream, st, s_out, work_at_s_out);
+    PBNG_LAUNCH_CHECK();
+}
+
+}  // namespace pbng

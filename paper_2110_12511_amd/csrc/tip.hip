@@ -1,6 +1,960 @@
+// Tip decomposition by two-phase peeling (Section 3.2).
+//
+// X is the peeled side, Y the other side (X = U, or X = V on the transposed
+// view).  Butterflies hold exactly two X-vertices, so peeling an active set
+// changes each surviving x' by the sum over active x of C(c(x,x'), 2), with
+// c the common-neighbour count; these updates from different active vertices
+// are disjoint butterflies and aggregate with plain atomics (Section 3.2).
+//
+// Coarse-grained phase (Algorithm 4 structure, tip form): per partition i,
+//   * work w_x = sum over y in N_x of the live degree of y (the wedge count
+//     of x, also the quantity of the batch rule in Section 5.1);
+//   * bound theta(i+1) = 1 + the smallest support whose cumulative alive work
+//     reaches the adaptive target (find_range);
+//   * support snapshot (the initialisation vector) and the first active set;
+//   * rounds: peel the active set by wedge traversal (or recount the remaining
+//     graph when the active set's wedges exceed the counting bound,
+//     Section 5.1); vertices whose support crosses below the bound form the
+//     next active set; peeled vertices are dropped from the Y lists
+//     (Section 5.2).
+// Fine-grained phase: each partition is peeled alone on the subgraph induced
+// by its vertices and all of Y, starting from the snapshot, in one persistent
+// kernel whose workgroups pop partitions from a queue sorted by decreasing
+// estimated work (Section 3.1.4).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+
+#include "dev_common.h"
 #include "pbng_internal.h"
+
 namespace pbng {
-void tip_decompose(Ctx &, const DevGraph &, int, const pbng_opts &, u64 *) {
-    throw Error(PBNG_E_UNSUPPORTED, "tip decomposition not built yet");
+
+enum : unsigned char { ST_ALIVE = 0, ST_ACTIVE = 1, ST_PEELED = 2 };
+
+constexpr i64 T_SMALL_W = 512, T_MEDIUM_W = 4096;
+
+struct TipCtl {
+    u64 bound;      // theta(i+1)
+    u64 s;          // selected support
+    u64 est_init;   // estimated work of the partition when its bound was chosen
+    u64 est_final;  // work of all vertices that joined the partition
+    double scale;   // scaling factor for the next target
+    u32 nF;         // current active-set size
+    u32 nF2;        // next active-set size
+    u64 wF;         // wedges of the current active set
+    u64 wF2;        // wedges of the next active set
+    u64 wedges;     // wedges walked by peeling kernels
+    u32 nbin[3];    // active-set bins
+    u32 next[3];    // work counters
+    u32 ndirty;     // Y lists to compact
+    u32 pad;
+};
+
+struct PeelArgs {
+    const i64 *xrow;
+    const i32 *xadj;
+    const i64 *yrow;
+    const i32 *yadj;
+    const i32 *ylen;
+    const i32 *items;
+    const u32 *nitems;
+    u32 *next;
+    const unsigned char *st;
+    u64 *sup;
+    u64 *w;
+    const u64 *bound;
+    i32 *nf;
+    u32 *nnf;
+    u32 *dcnt;
+    i32 *dtouch;
+    u32 *dntouch;
+    i64 nx;
+    u64 *wedges;
+};
+
+struct ItemSmem {
+    i32 *pre;
+    i64 *moff;
+    i32 *wave;
+    u64 *red;
+    i64 *bcast;
+};
+
+// Every wedge x -> y -> x' of an active x over the live Y lists; x' must be
+// alive.  Then for every touched x': its work loses c (one wedge per shared
+// y), and its support loses C(c, 2); a support that crosses below the bound
+// puts x' in the next active set (exactly once: supports only decrease).
+template <int BLOCK, class Acc>
+__device__ __forceinline__ void peel_item(const PeelArgs &a, i32 x, Acc &A, const ItemSmem &sm, u64 &wedges) {
+    const i64 jb = a.xrow[x], je = a.xrow[x + 1];
+    for (i64 cb = jb; cb < je; cb += BLOCK) {
+        i64 j = cb + threadIdx.x;
+        i32 pl = 0;
+        i64 moff = 0;
+        if (j < je) {
+            i32 y = a.xadj[j];
+            pl = a.ylen[y];
+            moff = a.yrow[y];
+        }
+        i32 tot;
+        i32 incl = block_incl_scan_i32<BLOCK>(pl, sm.wave, tot);
+        sm.pre[threadIdx.x] = incl;
+        sm.moff[threadIdx.x] = moff;
+        __syncthreads();
+        for (i32 k = threadIdx.x; k < tot; k += BLOCK) {
+            int lo = 0, hi = BLOCK - 1;
+            while (lo < hi) {
+                int md = (lo + hi) >> 1;
+                if (sm.pre[md] > k) hi = md; else lo = md + 1;
+            }
+            i32 before = lo ? sm.pre[lo - 1] : 0;
+            i32 xp = a.yadj[sm.moff[lo] + (k - before)];
+            if (xp == x) continue;
+            ++wedges;
+            if (a.st[xp] != ST_ALIVE) continue;
+            A.add(xp);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) sm.bcast[0] = A.entries();
+    __syncthreads();
+    const i64 ne = sm.bcast[0];
+    __syncthreads();
+    const u64 B = *a.bound;
+    for (i64 i = threadIdx.x; i < ne; i += BLOCK) {
+        i32 key;
+        u32 c32;
+        A.entry(i, key, c32);
+        if (key < 0 || c32 == 0) continue;
+        u64 cc = c32;
+        atomicAdd((unsigned long long *)&a.w[key], (unsigned long long)(0ull - cc));
+        if (cc < 2) continue;
+        u64 d = cc * (cc - 1) / 2;
+        u64 old = atomicAdd((unsigned long long *)&a.sup[key], (unsigned long long)(0ull - d));
+        if (old >= B && old - d < B) {
+            u32 p = atomicAdd(a.nnf, 1u);
+            a.nf[p] = key;
+        }
+    }
+    __syncthreads();
 }
+
+template <int BLOCK, int LOGCAP>
+__global__ __launch_bounds__(BLOCK) void k_tip_peel_hash(PeelArgs a, int bin) {
+    constexpr int CAP = 1 << LOGCAP;
+    __shared__ i32 s_keys[CAP];
+    __shared__ u32 s_vals[CAP];
+    __shared__ i32 s_pre[BLOCK];
+    __shared__ i64 s_moff[BLOCK];
+    __shared__ i32 s_wave[BLOCK / WAVE];
+    __shared__ u64 s_red[BLOCK / WAVE];
+    __shared__ i64 s_bcast[1];
+    __shared__ i32 s_item;
+    ItemSmem sm{s_pre, s_moff, s_wave, s_red, s_bcast};
+    LdsAcc A;
+    A.keys = s_keys;
+    A.vals = s_vals;
+    A.bids = nullptr;
+    const u32 n = a.nitems[bin];
+    u64 wedges = 0;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = (i32)atomicAdd(&a.next[bin], 1u);
+        __syncthreads();
+        const i32 item = s_item;
+        __syncthreads();
+        if ((u32)item >= n) break;
+        const i32 x = a.items[item];
+        const i64 wx = (i64)a.w[x];
+        int logcap = 6;
+        while ((i64(1) << logcap) < 2 * wx && logcap < LOGCAP) ++logcap;
+        A.init(logcap, threadIdx.x, BLOCK);
+        __syncthreads();
+        peel_item<BLOCK>(a, x, A, sm, wedges);
+    }
+    if (wedges) atomicAdd((unsigned long long *)a.wedges, (unsigned long long)wedges);
+}
+
+__global__ __launch_bounds__(256) void k_tip_peel_dense(PeelArgs a, int bin) {
+    constexpr int BLOCK = 256;
+    __shared__ i32 s_pre[BLOCK];
+    __shared__ i64 s_moff[BLOCK];
+    __shared__ i32 s_wave[BLOCK / WAVE];
+    __shared__ u64 s_red[BLOCK / WAVE];
+    __shared__ i64 s_bcast[1];
+    __shared__ i32 s_item;
+    ItemSmem sm{s_pre, s_moff, s_wave, s_red, s_bcast};
+    DenseAcc A;
+    A.c = a.dcnt + (i64)blockIdx.x * a.nx;
+    A.bids = nullptr;
+    A.touch = a.dtouch + (i64)blockIdx.x * a.nx;
+    A.ntouch = a.dntouch + blockIdx.x;
+    const u32 n = a.nitems[bin];
+    u64 wedges = 0;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = (i32)atomicAdd(&a.next[bin], 1u);
+        __syncthreads();
+        const i32 item = s_item;
+        __syncthreads();
+        if ((u32)item >= n) break;
+        peel_item<BLOCK>(a, a.items[item], A, sm, wedges);
+        A.reset(threadIdx.x, BLOCK);
+    }
+    if (wedges) atomicAdd((unsigned long long *)a.wedges, (unsigned long long)wedges);
+}
+
+// ------------------------------------------------------------------ CD helpers
+
+__global__ void k_bin_active(const i32 *F, const u32 *nF, const u64 *w, i32 *lists, i64 stride, u32 *nbin) {
+    const u32 n = *nF;
+    for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) {
+        i32 x = F[i];
+        u64 wx = w[x];
+        int b = wx <= (u64)T_SMALL_W ? 0 : (wx <= (u64)T_MEDIUM_W ? 1 : 2);
+        u32 p = atomicAdd(&nbin[b], 1u);
+        lists[b * stride + p] = x;
+    }
+}
+
+// w_x = sum of live Y degrees over N_x, one wave per row
+__global__ void k_work_full(const i64 *xrow, const i32 *xadj, const i32 *ydeg, const unsigned char *st, i64 nx, u64 *w) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const i64 wave = (blockIdx.x * (i64)blockDim.x + threadIdx.x) / WAVE;
+    const i64 nwaves = (i64)gridDim.x * blockDim.x / WAVE;
+    for (i64 x = wave; x < nx; x += nwaves) {
+        if (st && st[x] != ST_ALIVE) continue;
+        u64 s = 0;
+        for (i64 j = xrow[x] + lane; j < xrow[x + 1]; j += WAVE) s += (u64)ydeg[xadj[j]];
+        for (int d = WAVE / 2; d > 0; d >>= 1) s += __shfl_down(s, d, WAVE);
+        if (lane == 0) w[x] = s;
+    }
+}
+
+// Snapshot of the partition start (initialisation vector) and the first
+// active set: alive x with support below the bound.
+__global__ void k_frontier(unsigned char *st, const u64 *sup, const u64 *w, u64 *init, u64 *wsnap, i32 *part, i64 nx,
+                           TipCtl *ctl, i32 pid, int snapshot, i32 *F) {
+    const u64 B = ctl->bound;
+    for (i64 x = blockIdx.x * (i64)blockDim.x + threadIdx.x; x < nx; x += (i64)gridDim.x * blockDim.x) {
+        if (st[x] != ST_ALIVE) continue;
+        u64 s = sup[x];
+        if (snapshot) {
+            init[x] = s;
+            wsnap[x] = w[x];
+        }
+        if (s < B) {
+            st[x] = ST_ACTIVE;
+            part[x] = pid;
+            u32 p = atomicAdd(&ctl->nF, 1u);
+            F[p] = (i32)x;
+            atomicAdd((unsigned long long *)&ctl->wF, (unsigned long long)w[x]);
+        }
+    }
+}
+
+// Active vertices become peeled: their Y neighbours lose one live degree and
+// are queued for list compaction.  One wave per vertex.
+__global__ void k_retire(const i32 *F, const u32 *nF, const i64 *xrow, const i32 *xadj, unsigned char *st, i32 *ydeg,
+                         unsigned char *ydirty, i32 *dirty, u32 *ndirty, const u64 *wsnap, TipCtl *ctl, int dynamic) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const i64 wave = (blockIdx.x * (i64)blockDim.x + threadIdx.x) / WAVE;
+    const i64 nwaves = (i64)gridDim.x * blockDim.x / WAVE;
+    const u32 n = *nF;
+    for (i64 i = wave; i < n; i += nwaves) {
+        i32 x = F[i];
+        if (lane == 0) {
+            st[x] = ST_PEELED;
+            atomicAdd((unsigned long long *)&ctl->est_final, (unsigned long long)wsnap[x]);
+        }
+        for (i64 j = xrow[x] + lane; j < xrow[x + 1]; j += WAVE) {
+            i32 y = xadj[j];
+            atomicSub(&ydeg[y], 1);
+            if (dynamic) {
+                // byte flag per y: first setter queues y
+                unsigned int *word = (unsigned int *)(ydirty + (y & ~3));
+                unsigned int bit = 0xFFu << (8 * (y & 3));
+                unsigned int old = atomicOr(word, bit);
+                if ((old & bit) == 0) {
+                    u32 p = atomicAdd(ndirty, 1u);
+                    dirty[p] = y;
+                }
+            }
+        }
+    }
+}
+
+__global__ void k_activate(const i32 *F2, const u32 *nF2, unsigned char *st, i32 *part, const u64 *w, i32 pid, TipCtl *ctl) {
+    const u32 n = *nF2;
+    u64 s = 0;
+    for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) {
+        i32 x = F2[i];
+        st[x] = ST_ACTIVE;
+        part[x] = pid;
+        s += w[x];
+    }
+    for (int d = WAVE / 2; d > 0; d >>= 1) s += __shfl_down(s, d, WAVE);
+    if ((threadIdx.x & 63) == 0 && s) atomicAdd((unsigned long long *)&ctl->wF2, (unsigned long long)s);
+}
+
+// In-place compaction of dirty Y lists to their alive entries; one wave per
+// list, 64 entries per step with a ballot prefix.
+__global__ void k_compact(const i32 *dirty, const u32 *ndirty, const i64 *yrow, i32 *yadj, i32 *ylen,
+                          unsigned char *ydirty, const unsigned char *st) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const i64 wave = (blockIdx.x * (i64)blockDim.x + threadIdx.x) / WAVE;
+    const i64 nwaves = (i64)gridDim.x * blockDim.x / WAVE;
+    const u32 n = *ndirty;
+    const u64 lt = lane ? (~0ull >> (WAVE - lane)) : 0ull;
+    for (i64 i = wave; i < n; i += nwaves) {
+        i32 y = dirty[i];
+        const i64 b = yrow[y];
+        const i32 len = ylen[y];
+        i32 out = 0;
+        for (i32 k0 = 0; k0 < len; k0 += WAVE) {
+            i32 k = k0 + lane;
+            i32 x = k < len ? yadj[b + k] : -1;
+            bool keep = k < len && st[x] == ST_ALIVE;
+            u64 bal = __ballot(keep);
+            if (keep) yadj[b + out + __popcll(bal & lt)] = x;
+            out += __popcll(bal);
+        }
+        if (lane == 0) {
+            ylen[y] = out;
+            ydirty[y] = 0;
+        }
+    }
+}
+
+__global__ void k_set_bound(TipCtl *ctl, int last) {
+    ctl->bound = last ? ~0ull : ctl->s + 1;
+    ctl->nF = 0;
+    ctl->wF = 0;
+    ctl->est_final = 0;
+}
+
+__global__ void k_next_round(TipCtl *ctl) {
+    // next active set becomes current; counters of the round are cleared
+    ctl->nF = ctl->nF2;
+    ctl->wF = ctl->wF2;
+    ctl->nF2 = 0;
+    ctl->wF2 = 0;
+    ctl->nbin[0] = ctl->nbin[1] = ctl->nbin[2] = 0;
+    ctl->next[0] = ctl->next[1] = ctl->next[2] = 0;
+    ctl->ndirty = 0;
+}
+
+__global__ void k_scale(TipCtl *ctl) {
+    // s_{i+1} = initial estimate / final estimate of partition i
+    double fin = (double)ctl->est_final;
+    ctl->scale = fin > 0 ? (double)ctl->est_init / fin : 1.0;
+    if (!(ctl->scale > 0)) ctl->scale = 1.0;
+}
+
+__global__ void k_alive_label(const unsigned char *st, const i32 *gid, i64 n, i64 xoff, i64 nx, unsigned char *alive) {
+    for (i64 l = blockIdx.x * (i64)blockDim.x + threadIdx.x; l < n; l += (i64)gridDim.x * blockDim.x) {
+        i64 g = gid[l] - xoff;
+        alive[l] = (g >= 0 && g < nx) ? (st[g] == ST_ALIVE) : 1;
+    }
+}
+
+__global__ void k_from_label(const u64 *sup_label, const i32 *label, i64 xoff, i64 nx, const unsigned char *st, u64 *sup) {
+    for (i64 x = blockIdx.x * (i64)blockDim.x + threadIdx.x; x < nx; x += (i64)gridDim.x * blockDim.x)
+        if (st[x] == ST_ALIVE) sup[x] = sup_label[label[x + xoff]];
+}
+
+__global__ void k_min_deg_sum(const i64 *xrow, const i32 *xadj, const i32 *ydeg, i64 nx, u64 *out) {
+    // sum over edges of min(d_x, d_y): the wedge bound of one counting pass
+    u64 s = 0;
+    for (i64 x = blockIdx.x * (i64)blockDim.x + threadIdx.x; x < nx; x += (i64)gridDim.x * blockDim.x) {
+        i64 dx = xrow[x + 1] - xrow[x];
+        for (i64 j = xrow[x]; j < xrow[x + 1]; ++j) {
+            i64 dy = ydeg[xadj[j]];
+            s += (u64)(dx < dy ? dx : dy);
+        }
+    }
+    for (int d = WAVE / 2; d > 0; d >>= 1) s += __shfl_down(s, d, WAVE);
+    if ((threadIdx.x & 63) == 0) atomicAdd((unsigned long long *)out, (unsigned long long)s);
+}
+
+__global__ void k_degrees_y(const i64 *yrow, i64 ny, i32 *ydeg, i32 *ylen) {
+    for (i64 y = blockIdx.x * (i64)blockDim.x + threadIdx.x; y < ny; y += (i64)gridDim.x * blockDim.x) {
+        i32 d = (i32)(yrow[y + 1] - yrow[y]);
+        ydeg[y] = d;
+        ylen[y] = d;
+    }
+}
+
+// Seeded random bounds (schedule-invariance tests): theta(i+1) drawn between
+// the smallest alive support + 1 and the largest alive support + 1.
+__global__ void k_random_bound(const u64 *sup, const unsigned char *st, i64 nx, u64 *mn, u64 *mx) {
+    u64 a = ~0ull, b = 0;
+    for (i64 x = blockIdx.x * (i64)blockDim.x + threadIdx.x; x < nx; x += (i64)gridDim.x * blockDim.x) {
+        if (st[x] != ST_ALIVE) continue;
+        u64 s = sup[x];
+        a = s < a ? s : a;
+        b = s > b ? s : b;
+    }
+    for (int d = WAVE / 2; d > 0; d >>= 1) {
+        u64 o = __shfl_down(a, d, WAVE);
+        a = o < a ? o : a;
+        o = __shfl_down(b, d, WAVE);
+        b = o > b ? o : b;
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMin((unsigned long long *)mn, (unsigned long long)a);
+        atomicMax((unsigned long long *)mx, (unsigned long long)b);
+    }
+}
+
+__device__ inline u64 splitmix64(u64 z) {
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__global__ void k_random_pick(TipCtl *ctl, const u64 *mn, const u64 *mx, u64 seed, int i) {
+    u64 lo = *mn, hi = *mx;
+    u64 span = hi - lo + 1;
+    u64 r = splitmix64(seed * 1000003ull + (u64)i);
+    // bias toward small steps so that several partitions form
+    u64 step = span > 1 ? r % (span / 4 + 1) : 0;
+    ctl->s = lo + step;
+}
+
+// ------------------------------------------------------------------ FD
+
+struct FdArgs {
+    const i64 *xrow;
+    const i32 *xadj;
+    const i32 *xs;       // X ids grouped by partition
+    const i64 *poff;     // [np+1]
+    const i32 *loc;      // position of x inside its partition
+    const i32 *yps;      // Y lists grouped by partition
+    const i64 *flo;      // per X-CSR entry: start of N_y restricted to p(x)
+    const i32 *flen;     // per X-CSR entry: its length
+    const i32 *queue;    // partitions, decreasing work
+    i32 np;
+    u32 *head;
+    const u64 *init;
+    u64 *theta;
+    // per-workgroup scratch, stride maxni
+    u64 *lsup;
+    unsigned char *lst;
+    u32 *lcnt;
+    i32 *ltouch;
+    i32 *lbatch;
+    i64 maxni;
+    u64 *wedges;
+};
+
+// One workgroup peels one partition at a time with sequential bottom-up
+// peeling on its induced subgraph: take every alive vertex at the current
+// minimum support k (peeling a whole level at once is exact because the
+// max(k, .) clamps of one level commute), then for each of them walk its
+// wedges inside the partition and lower the supports of the other alive
+// vertices to max(k, support - C(c, 2)).
+__global__ __launch_bounds__(256) void k_tip_fd(FdArgs a) {
+    constexpr int BLOCK = 256;
+    __shared__ i32 s_pre[BLOCK];
+    __shared__ i64 s_moff[BLOCK];
+    __shared__ i32 s_wave[BLOCK / WAVE];
+    __shared__ u64 s_red[BLOCK / WAVE];
+    __shared__ i32 s_item;
+    __shared__ u32 s_cnt[2];
+    u64 *lsup = a.lsup + blockIdx.x * a.maxni;
+    unsigned char *lst = a.lst + blockIdx.x * a.maxni;
+    u32 *lcnt = a.lcnt + blockIdx.x * a.maxni;
+    i32 *ltouch = a.ltouch + blockIdx.x * a.maxni;
+    i32 *lbatch = a.lbatch + blockIdx.x * a.maxni;
+    u64 wedges = 0;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = (i32)atomicAdd(a.head, 1u);
+        __syncthreads();
+        const i32 qi = s_item;
+        __syncthreads();
+        if (qi >= a.np) break;
+        const i32 pid = a.queue[qi];
+        const i64 base = a.poff[pid];
+        const i32 ni = (i32)(a.poff[pid + 1] - base);
+        for (i32 k = threadIdx.x; k < ni; k += BLOCK) {
+            st_coherent(&lsup[k], a.init[a.xs[base + k]]);
+            st_coherent(&lst[k], (unsigned char)1);
+            st_coherent(&lcnt[k], 0u);
+        }
+        __syncthreads();
+        i32 remaining = ni;
+        while (remaining > 0) {
+            u64 mn = ~0ull;
+            for (i32 k = threadIdx.x; k < ni; k += BLOCK)
+                if (ld_coherent(&lst[k]) == 1) {
+                    u64 s = ld_coherent(&lsup[k]);
+                    mn = s < mn ? s : mn;
+                }
+            const u64 kmin = block_min_u64<BLOCK>(mn, s_red);
+            if (threadIdx.x == 0) s_cnt[0] = 0;
+            __syncthreads();
+            for (i32 k = threadIdx.x; k < ni; k += BLOCK) {
+                if (ld_coherent(&lst[k]) == 1 && ld_coherent(&lsup[k]) == kmin) {
+                    u32 p = atomicAdd(&s_cnt[0], 1u);
+                    st_coherent(&lbatch[p], k);
+                    st_coherent(&lst[k], (unsigned char)2);
+                    a.theta[a.xs[base + k]] = kmin;
+                }
+            }
+            __syncthreads();
+            const i32 nb = (i32)s_cnt[0];
+            __syncthreads();
+            for (i32 b = 0; b < nb; ++b) {
+                const i32 x = a.xs[base + ld_coherent(&lbatch[b])];
+                if (threadIdx.x == 0) s_cnt[1] = 0;
+                __syncthreads();
+                const i64 jb = a.xrow[x], je = a.xrow[x + 1];
+                for (i64 cb = jb; cb < je; cb += BLOCK) {
+                    i64 j = cb + threadIdx.x;
+                    i32 pl = 0;
+                    i64 moff = 0;
+                    if (j < je) {
+                        pl = a.flen[j];
+                        moff = a.flo[j];
+                    }
+                    i32 tot;
+                    i32 incl = block_incl_scan_i32<BLOCK>(pl, s_wave, tot);
+                    s_pre[threadIdx.x] = incl;
+                    s_moff[threadIdx.x] = moff;
+                    __syncthreads();
+                    for (i32 k = threadIdx.x; k < tot; k += BLOCK) {
+                        int lo = 0, hi = BLOCK - 1;
+                        while (lo < hi) {
+                            int md = (lo + hi) >> 1;
+                            if (s_pre[md] > k) hi = md; else lo = md + 1;
+                        }
+                        i32 before = lo ? s_pre[lo - 1] : 0;
+                        i32 xp = a.yps[s_moff[lo] + (k - before)];
+                        if (xp == x) continue;
+                        ++wedges;
+                        i32 kp = a.loc[xp];
+                        if (ld_coherent(&lst[kp]) != 1) continue;
+                        if (atomicAdd(&lcnt[kp], 1u) == 0) {
+                            u32 t = atomicAdd(&s_cnt[1], 1u);
+                            st_coherent(&ltouch[t], kp);
+                        }
+                    }
+                    __syncthreads();
+                }
+                const u32 nt = s_cnt[1];
+                for (u32 t = threadIdx.x; t < nt; t += BLOCK) {
+                    i32 kp = ld_coherent(&ltouch[t]);
+                    u64 cc = atomicExch(&lcnt[kp], 0u);
+                    if (cc >= 2) {
+                        u64 d = cc * (cc - 1) / 2;
+                        u64 s = ld_coherent(&lsup[kp]);
+                        u64 ns = s > d ? s - d : 0;
+                        st_coherent(&lsup[kp], ns < kmin ? kmin : ns);
+                    }
+                }
+                __syncthreads();
+            }
+            for (i32 b = threadIdx.x; b < nb; b += BLOCK) st_coherent(&lst[ld_coherent(&lbatch[b])], (unsigned char)0);
+            remaining -= nb;
+            __syncthreads();
+        }
+    }
+    if (wedges) atomicAdd((unsigned long long *)a.wedges, (unsigned long long)wedges);
+}
+
+// ---- FD preparation kernels
+
+__global__ void k_part_keys(const i32 *part, i64 nx, u64 *keys, i32 *vals, u32 *pcount) {
+    for (i64 x = blockIdx.x * (i64)blockDim.x + threadIdx.x; x < nx; x += (i64)gridDim.x * blockDim.x) {
+        keys[x] = (u64)part[x];
+        vals[x] = (i32)x;
+        atomicAdd(&pcount[part[x]], 1u);
+    }
+}
+
+__global__ void k_u32_to_i64_t(const u32 *a, i64 n, i64 *b) {
+    for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) b[i] = a[i];
+}
+
+__global__ void k_loc(const i32 *xs, const i32 *part, const i64 *poff, i64 nx, i32 *loc) {
+    for (i64 k = blockIdx.x * (i64)blockDim.x + threadIdx.x; k < nx; k += (i64)gridDim.x * blockDim.x) {
+        i32 x = xs[k];
+        loc[x] = (i32)(k - poff[part[x]]);
+    }
+}
+
+__device__ inline i64 row_of_t(const i64 *row, i64 n, i64 e) {
+    i64 a = 0, b = n;
+    while (a < b) {
+        i64 c = (a + b + 1) >> 1;
+        if (row[c] <= e) a = c; else b = c - 1;
+    }
+    return a;
+}
+
+__global__ void k_ypart_keys(const i64 *yrow, const i32 *yadj_orig, const i32 *part, i64 ny, i64 m, i32 np, u64 *keys, i32 *vals) {
+    for (i64 e = blockIdx.x * (i64)blockDim.x + threadIdx.x; e < m; e += (i64)gridDim.x * blockDim.x) {
+        i64 y = row_of_t(yrow, ny, e);
+        i32 x = yadj_orig[e];
+        keys[e] = (u64)y * (u64)np + (u64)part[x];
+        vals[e] = x;
+    }
+}
+
+// For X-CSR entry (x, y): the run of N_y (grouped by partition) whose
+// vertices share x's partition; work_p += its length - 1.
+__global__ void k_fd_segments(const i64 *xrow, const i32 *xadj, i64 nx, i64 mx, const i64 *yrow, const i32 *yps,
+                              const i32 *part, i64 *flo, i32 *flen, u64 *work) {
+    for (i64 j = blockIdx.x * (i64)blockDim.x + threadIdx.x; j < mx; j += (i64)gridDim.x * blockDim.x) {
+        i64 x = row_of_t(xrow, nx, j);
+        i32 p = part[x];
+        i32 y = xadj[j];
+        i64 a = yrow[y], b = yrow[y + 1];
+        i64 lo = a, hi = b;
+        while (lo < hi) {  // first entry with part >= p
+            i64 c = (lo + hi) >> 1;
+            if (part[yps[c]] < p) lo = c + 1; else hi = c;
+        }
+        i64 s = lo;
+        hi = b;
+        while (lo < hi) {  // first entry with part > p
+            i64 c = (lo + hi) >> 1;
+            if (part[yps[c]] <= p) lo = c + 1; else hi = c;
+        }
+        flo[j] = s;
+        flen[j] = (i32)(lo - s);
+        atomicAdd((unsigned long long *)&work[p], (unsigned long long)(lo - s - 1));
+    }
+}
+
+__global__ void k_lpt_keys(const u64 *work, i32 np, u64 maxw, u64 *keys, i32 *vals, u64 *wmax, u64 *wsum) {
+    for (i64 p = blockIdx.x * (i64)blockDim.x + threadIdx.x; p < np; p += (i64)gridDim.x * blockDim.x) {
+        keys[p] = maxw - work[p];
+        vals[p] = (i32)p;
+        atomicMax((unsigned long long *)wmax, (unsigned long long)work[p]);
+        atomicAdd((unsigned long long *)wsum, (unsigned long long)work[p]);
+    }
+}
+
+__global__ void k_max_u64(const u64 *a, i64 n, u64 *out) {
+    u64 m = 0;
+    for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) m = a[i] > m ? a[i] : m;
+    for (int d = WAVE / 2; d > 0; d >>= 1) {
+        u64 o = __shfl_down(m, d, WAVE);
+        m = o > m ? o : m;
+    }
+    if ((threadIdx.x & 63) == 0) atomicMax((unsigned long long *)out, (unsigned long long)m);
+}
+
+// ------------------------------------------------------------------ host
+
+static double now_ms() {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Default P and the work-efficiency clamp of Section 4.2 (tip: P at most the
+// wedge total over n log2 n, n = vertices of the peeled side).
+static int tip_partitions(const pbng_opts &o, u64 wedge_total, i64 nx) {
+    if (o.P > 0) return o.P;
+    int P = 150;
+    double nlogn = (double)nx * std::log2((double)std::max<i64>(nx, 2));
+    double cap = nlogn > 0 ? std::floor((double)wedge_total / nlogn) : 1.0;
+    if (cap < 1) cap = 1;
+    if (P > cap) P = (int)cap;
+    return std::max(P, 1);
+}
+
+void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 *theta) {
+    hipStream_t s = c.stream;
+    const i64 nx = side == 0 ? G.n_u : G.n_v;
+    const i64 ny = side == 0 ? G.n_v : G.n_u;
+    const i64 m = G.m;
+    const i64 xoff = side == 0 ? 0 : G.n_u;
+    if (nx == 0) return;
+    const i64 *xrow = side == 0 ? G.urow : G.vrow;
+    const i32 *xadj = side == 0 ? G.ucol : G.vadj;
+    const i64 *yrow = side == 0 ? G.vrow : G.urow;
+    const i32 *yadj0 = side == 0 ? G.vadj : G.ucol;
+    const bool dynamic = !(o.flags & PBNG_F_NO_DYNAMIC);
+    const bool batch = !(o.flags & PBNG_F_NO_BATCH);
+    double t0 = now_ms();
+
+    // ---- counting
+    u64 *sup = c.alloc<u64>(nx);
+    {
+        u64 *sl = c.alloc<u64>(G.n);
+        u64 w = count_pass(c, G, sl, nullptr, nullptr);
+        c.stats.wedges_count += w;
+        gather_side(c, G, sl, side, sup);
+    }
+    PBNG_HIP(hipStreamSynchronize(s));
+    double t1 = now_ms();
+    c.stats.ms_count = t1 - t0;
+
+    // ---- state
+    unsigned char *st = c.alloc<unsigned char>(nx);
+    i32 *part = c.alloc<i32>(nx);
+    u64 *init = c.alloc<u64>(nx);
+    u64 *w = c.alloc<u64>(nx);
+    u64 *wsnap = c.alloc<u64>(nx);
+    i32 *ydeg = c.alloc<i32>(ny);
+    i32 *ylen = c.alloc<i32>(ny);
+    unsigned char *ydirty = c.alloc<unsigned char>(ny + 4);
+    i32 *dirty = c.alloc<i32>(ny);
+    i32 *yadj = c.alloc<i32>(m);
+    i32 *F = c.alloc<i32>(nx);
+    i32 *F2 = c.alloc<i32>(nx);
+    i32 *bins = c.alloc<i32>(3 * nx);
+    TipCtl *ctl = c.alloc<TipCtl>(1);
+    PBNG_HIP(hipMemsetAsync(st, 0, nx, s));
+    PBNG_HIP(hipMemsetAsync(ydirty, 0, ny + 4, s));
+    PBNG_HIP(hipMemsetAsync(ctl, 0, sizeof(TipCtl), s));
+    if (m) PBNG_HIP(hipMemcpyAsync(yadj, yadj0, sizeof(i32) * m, hipMemcpyDeviceToDevice, s));
+    if (ny) hipLaunchKernelGGL(k_degrees_y, dim3(grid_1d(ny)), dim3(256), 0, s, yrow, ny, ydeg, ylen);
+    hipLaunchKernelGGL(k_work_full, dim3(grid_1d(nx * WAVE)), dim3(256), 0, s, xrow, xadj, (const i32 *)ydeg,
+                       (const unsigned char *)nullptr, nx, w);
+    PBNG_LAUNCH_CHECK();
+    u64 *tmp = c.alloc<u64>(2);
+    PBNG_HIP(hipMemsetAsync(tmp, 0, 2 * sizeof(u64), s));
+    hipLaunchKernelGGL(k_min_deg_sum, dim3(grid_1d(nx)), dim3(256), 0, s, xrow, xadj, (const i32 *)ydeg, nx, tmp);
+    PBNG_LAUNCH_CHECK();
+    const u64 wedge_cnt_bound = read_scalar<u64>(c, tmp);
+    const u64 wedge_total = reduce_sum_u64(c, w, nx);
+    const int P = tip_partitions(o, wedge_total, nx);
+    c.stats.P_used = P;
+    {
+        double one = 1.0;
+        PBNG_HIP(hipMemcpyAsync(&ctl->scale, &one, sizeof(double), hipMemcpyHostToDevice, s));
+    }
+    // dense scratch for heavy active vertices
+    const int slots = c.num_cu;
+    u32 *dcnt = c.alloc<u32>((i64)slots * nx);
+    i32 *dtouch = c.alloc<i32>((i64)slots * nx);
+    u32 *dntouch = c.alloc<u32>(slots);
+    PBNG_HIP(hipMemsetAsync(dcnt, 0, sizeof(u32) * slots * nx, s));
+    PBNG_HIP(hipMemsetAsync(dntouch, 0, sizeof(u32) * slots, s));
+    unsigned char *alive_label = c.alloc<unsigned char>(G.n);
+    u64 *sup_label = c.alloc<u64>(G.n);
+    u64 *rmin = c.alloc<u64>(2);
+
+    PeelArgs pa{};
+    pa.xrow = xrow;
+    pa.xadj = xadj;
+    pa.yrow = yrow;
+    pa.yadj = yadj;
+    pa.ylen = ylen;
+    pa.nitems = ctl->nbin;
+    pa.next = ctl->next;
+    pa.st = st;
+    pa.sup = sup;
+    pa.w = w;
+    pa.bound = &ctl->bound;
+    pa.nnf = &ctl->nF2;
+    pa.dcnt = dcnt;
+    pa.dtouch = dtouch;
+    pa.dntouch = dntouch;
+    pa.nx = nx;
+    pa.wedges = &ctl->wedges;
+
+    struct HostView {
+        u32 nF;
+        u64 wF;
+    };
+    i64 n_alive = nx;
+    int pid = 0;
+    u64 rho = 0, recounts = 0, recount_wedges = 0;
+    const int gx = grid_1d(nx);
+    while (n_alive > 0) {
+        const bool last = (P - pid) <= 1;
+        if (!last) {
+            if (o.bound_rule == PBNG_BOUND_RANDOM) {
+                u64 init2[2] = {~0ull, 0};
+                PBNG_HIP(hipMemcpyAsync(rmin, init2, sizeof(init2), hipMemcpyHostToDevice, s));
+                hipLaunchKernelGGL(k_random_bound, dim3(gx), dim3(256), 0, s, (const u64 *)sup, (const unsigned char *)st, nx,
+                                   rmin, rmin + 1);
+                hipLaunchKernelGGL(k_random_pick, dim3(1), dim3(1), 0, s, ctl, (const u64 *)rmin, (const u64 *)(rmin + 1),
+                                   (u64)o.seed, pid);
+                PBNG_LAUNCH_CHECK();
+            } else {
+                weighted_select(c, sup, w, st, ST_ALIVE, nx, nullptr, &ctl->scale, P - pid, &ctl->s, &ctl->est_init);
+            }
+        }
+        hipLaunchKernelGGL(k_set_bound, dim3(1), dim3(1), 0, s, ctl, last ? 1 : 0);
+        hipLaunchKernelGGL(k_frontier, dim3(gx), dim3(256), 0, s, st, (const u64 *)sup, (const u64 *)w, init, wsnap, part,
+                           nx, ctl, pid, 1, F);
+        PBNG_LAUNCH_CHECK();
+        HostView hv;
+        PBNG_HIP(hipMemcpyAsync(&hv.nF, &ctl->nF, sizeof(u32), hipMemcpyDeviceToHost, s));
+        PBNG_HIP(hipMemcpyAsync(&hv.wF, &ctl->wF, sizeof(u64), hipMemcpyDeviceToHost, s));
+        PBNG_HIP(hipStreamSynchronize(s));
+        while (hv.nF > 0) {
+            ++rho;
+            const u32 nF = hv.nF;
+            const int gw = grid_1d((i64)nF * WAVE);
+            if ((i64)nF == n_alive) {
+                // everything left joins this partition: no updates needed
+                hipLaunchKernelGGL(k_retire, dim3(gw), dim3(256), 0, s, (const i32 *)F, (const u32 *)&ctl->nF, xrow, xadj, st,
+                                   ydeg, ydirty, dirty, &ctl->ndirty, (const u64 *)wsnap, ctl, 0);
+                PBNG_LAUNCH_CHECK();
+                n_alive = 0;
+                hipLaunchKernelGGL(k_next_round, dim3(1), dim3(1), 0, s, ctl);
+                break;
+            }
+            if (batch && hv.wF > wedge_cnt_bound) {
+                // Section 5.1: recount the remaining graph instead of peeling
+                hipLaunchKernelGGL(k_retire, dim3(gw), dim3(256), 0, s, (const i32 *)F, (const u32 *)&ctl->nF, xrow, xadj, st,
+                                   ydeg, ydirty, dirty, &ctl->ndirty, (const u64 *)wsnap, ctl, dynamic ? 1 : 0);
+                hipLaunchKernelGGL(k_alive_label, dim3(grid_1d(G.n)), dim3(256), 0, s, (const unsigned char *)st,
+                                   (const i32 *)G.gid, G.n, xoff, nx, alive_label);
+                PBNG_LAUNCH_CHECK();
+                recount_wedges += count_pass(c, G, sup_label, nullptr, alive_label);
+                hipLaunchKernelGGL(k_from_label, dim3(gx), dim3(256), 0, s, (const u64 *)sup_label, (const i32 *)G.label, xoff,
+                                   nx, (const unsigned char *)st, sup);
+                hipLaunchKernelGGL(k_work_full, dim3(grid_1d(nx * WAVE)), dim3(256), 0, s, xrow, xadj, (const i32 *)ydeg,
+                                   (const unsigned char *)st, nx, w);
+                PBNG_LAUNCH_CHECK();
+                ++recounts;
+                n_alive -= nF;
+                if (dynamic) {
+                    hipLaunchKernelGGL(k_compact, dim3(grid_1d((i64)ny * WAVE)), dim3(256), 0, s, (const i32 *)dirty,
+                                       (const u32 *)&ctl->ndirty, yrow, yadj, ylen, ydirty, (const unsigned char *)st);
+                    PBNG_LAUNCH_CHECK();
+                }
+                hipLaunchKernelGGL(k_next_round, dim3(1), dim3(1), 0, s, ctl);
+                hipLaunchKernelGGL(k_frontier, dim3(gx), dim3(256), 0, s, st, (const u64 *)sup, (const u64 *)w, init, wsnap,
+                                   part, nx, ctl, pid, 0, F);
+                PBNG_LAUNCH_CHECK();
+            } else {
+                pa.items = bins;
+                pa.nf = F2;
+                hipLaunchKernelGGL(k_bin_active, dim3(grid_1d(nF)), dim3(256), 0, s, (const i32 *)F, (const u32 *)&ctl->nF,
+                                   (const u64 *)w, bins, nx, ctl->nbin);
+                PBNG_LAUNCH_CHECK();
+                PeelArgs pd = pa;
+                pd.items = bins + 2 * nx;
+                hipLaunchKernelGGL(k_tip_peel_dense, dim3(std::min<i64>(slots, nF)), dim3(256), 0, s, pd, 2);
+                PeelArgs pm = pa;
+                pm.items = bins + nx;
+                hipLaunchKernelGGL((k_tip_peel_hash<256, 13>), dim3(std::min<i64>((i64)c.num_cu * 2, nF)), dim3(256), 0, s, pm, 1);
+                hipLaunchKernelGGL((k_tip_peel_hash<64, 10>), dim3(std::min<i64>((i64)c.num_cu * 16, nF)), dim3(64), 0, s, pa, 0);
+                PBNG_LAUNCH_CHECK();
+                hipLaunchKernelGGL(k_retire, dim3(gw), dim3(256), 0, s, (const i32 *)F, (const u32 *)&ctl->nF, xrow, xadj, st,
+                                   ydeg, ydirty, dirty, &ctl->ndirty, (const u64 *)wsnap, ctl, dynamic ? 1 : 0);
+                hipLaunchKernelGGL(k_activate, dim3(grid_1d(nx)), dim3(256), 0, s, (const i32 *)F2, (const u32 *)&ctl->nF2, st,
+                                   part, (const u64 *)w, pid, ctl);
+                PBNG_LAUNCH_CHECK();
+                if (dynamic) {
+                    hipLaunchKernelGGL(k_compact, dim3(grid_1d((i64)ny * WAVE)), dim3(256), 0, s, (const i32 *)dirty,
+                                       (const u32 *)&ctl->ndirty, yrow, yadj, ylen, ydirty, (const unsigned char *)st);
+                    PBNG_LAUNCH_CHECK();
+                }
+                n_alive -= nF;
+                hipLaunchKernelGGL(k_next_round, dim3(1), dim3(1), 0, s, ctl);
+                std::swap(F, F2);
+            }
+            PBNG_HIP(hipMemcpyAsync(&hv.nF, &ctl->nF, sizeof(u32), hipMemcpyDeviceToHost, s));
+            PBNG_HIP(hipMemcpyAsync(&hv.wF, &ctl->wF, sizeof(u64), hipMemcpyDeviceToHost, s));
+            PBNG_HIP(hipStreamSynchronize(s));
+        }
+        hipLaunchKernelGGL(k_scale, dim3(1), dim3(1), 0, s, ctl);
+        PBNG_LAUNCH_CHECK();
+        ++pid;
+    }
+    const i32 np = pid;
+    c.stats.wedges_cd = read_scalar<u64>(c, &ctl->wedges) + recount_wedges;
+    c.stats.rho = rho;
+    c.stats.recounts = recounts;
+    c.stats.partitions = np;
+    double t2 = now_ms();
+    c.stats.ms_cd = t2 - t1;
+
+    // ---- FD preparation: vertices and Y lists grouped by partition
+    u64 *pk = c.alloc<u64>(std::max<i64>(nx, m));
+    i32 *pv = c.alloc<i32>(std::max<i64>(nx, m));
+    u32 *pcount = c.alloc<u32>(np);
+    PBNG_HIP(hipMemsetAsync(pcount, 0, sizeof(u32) * np, s));
+    hipLaunchKernelGGL(k_part_keys, dim3(gx), dim3(256), 0, s, (const i32 *)part, nx, pk, pv, pcount);
+    PBNG_LAUNCH_CHECK();
+    u64 *sk;
+    i32 *xs;
+    radix_sort_u64(c, pk, pv, nx, bits_for((u64)np), &sk, &xs);
+    i64 *pc64 = c.alloc<i64>(np);
+    i64 *poff = c.alloc<i64>(np + 1);
+    hipLaunchKernelGGL(k_u32_to_i64_t, dim3(grid_1d(np)), dim3(256), 0, s, (const u32 *)pcount, (i64)np, pc64);
+    exclusive_scan<i64>(c, pc64, poff, np);
+    i32 *loc = c.alloc<i32>(nx);
+    hipLaunchKernelGGL(k_loc, dim3(gx), dim3(256), 0, s, (const i32 *)xs, (const i32 *)part, (const i64 *)poff, nx, loc);
+    PBNG_LAUNCH_CHECK();
+    u64 *yk = c.alloc<u64>(m);
+    i32 *yv = c.alloc<i32>(m);
+    i32 *yps = yv;
+    i64 *flo = c.alloc<i64>(m);
+    i32 *flen = c.alloc<i32>(m);
+    u64 *work = c.alloc<u64>(np);
+    PBNG_HIP(hipMemsetAsync(work, 0, sizeof(u64) * np, s));
+    if (m) {
+        hipLaunchKernelGGL(k_ypart_keys, dim3(grid_1d(m)), dim3(256), 0, s, yrow, yadj0, (const i32 *)part, ny, m, np, yk, yv);
+        PBNG_LAUNCH_CHECK();
+        u64 *ysk;
+        radix_sort_u64(c, yk, yv, m, bits_for((u64)ny * (u64)np), &ysk, &yps);
+        hipLaunchKernelGGL(k_fd_segments, dim3(grid_1d(m)), dim3(256), 0, s, xrow, xadj, nx, m, yrow, (const i32 *)yps,
+                           (const i32 *)part, flo, flen, work);
+        PBNG_LAUNCH_CHECK();
+    }
+    // LPT order
+    u64 *wm = c.alloc<u64>(3);
+    PBNG_HIP(hipMemsetAsync(wm, 0, 3 * sizeof(u64), s));
+    hipLaunchKernelGGL(k_max_u64, dim3(grid_1d(np)), dim3(256), 0, s, (const u64 *)work, (i64)np, wm);
+    const u64 maxw = read_scalar<u64>(c, wm);
+    u64 *lk = c.alloc<u64>(np);
+    i32 *lv = c.alloc<i32>(np);
+    hipLaunchKernelGGL(k_lpt_keys, dim3(grid_1d(np)), dim3(256), 0, s, (const u64 *)work, np, maxw, lk, lv, wm + 1, wm + 2);
+    PBNG_LAUNCH_CHECK();
+    u64 *lks;
+    i32 *queue;
+    radix_sort_u64(c, lk, lv, np, bits_for(maxw), &lks, &queue);
+    c.stats.fd_work_max = read_scalar<u64>(c, wm + 1);
+    c.stats.fd_work_sum = read_scalar<u64>(c, wm + 2);
+    // largest partition for scratch sizing
+    i64 *maxni_d = reinterpret_cast<i64 *>(c.alloc<u64>(1));
+    PBNG_HIP(hipMemsetAsync(maxni_d, 0, sizeof(u64), s));
+    hipLaunchKernelGGL(k_max_u64, dim3(grid_1d(np)), dim3(256), 0, s, (const u64 *)pc64, (i64)np, (u64 *)maxni_d);
+    const i64 maxni = std::max<i64>(read_scalar<i64>(c, maxni_d), 1);
+    PBNG_HIP(hipStreamSynchronize(s));
+    double t3 = now_ms();
+    c.stats.ms_fd_prep = t3 - t2;
+
+    // ---- FD
+    const int fdblocks = (int)std::min<i64>(np, (i64)c.num_cu * 2);
+    FdArgs fa{};
+    fa.xrow = xrow;
+    fa.xadj = xadj;
+    fa.xs = xs;
+    fa.poff = poff;
+    fa.loc = loc;
+    fa.yps = yps;
+    fa.flo = flo;
+    fa.flen = flen;
+    fa.queue = queue;
+    fa.np = np;
+    fa.head = c.alloc<u32>(1);
+    PBNG_HIP(hipMemsetAsync(fa.head, 0, sizeof(u32), s));
+    fa.init = init;
+    fa.theta = theta;
+    fa.maxni = maxni;
+    fa.lsup = c.alloc<u64>((i64)fdblocks * maxni);
+    fa.lst = c.alloc<unsigned char>((i64)fdblocks * maxni);
+    fa.lcnt = c.alloc<u32>((i64)fdblocks * maxni);
+    fa.ltouch = c.alloc<i32>((i64)fdblocks * maxni);
+    fa.lbatch = c.alloc<i32>((i64)fdblocks * maxni);
+    fa.wedges = c.alloc<u64>(1);
+    PBNG_HIP(hipMemsetAsync(fa.wedges, 0, sizeof(u64), s));
+    hipLaunchKernelGGL(k_tip_fd, dim3(fdblocks), dim3(256), 0, s, fa);
+    PBNG_LAUNCH_CHECK();
+    c.stats.wedges_fd = read_scalar<u64>(c, fa.wedges);
+    c.stats.ms_fd = now_ms() - t3;
+    c.stats.wedges = c.stats.wedges_count + c.stats.wedges_cd + c.stats.wedges_fd;
+}
+
 }  // namespace pbng

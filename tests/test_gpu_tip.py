@@ -1,0 +1,111 @@
+"""Parity of tip decomposition on the GPU with the CPU oracle (bit-exact),
+plus invariance of the result under every schedule knob."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2110_12511_amd as pb
+import synth
+from gpu_util import u64, golden, check_golden
+
+pytestmark = pytest.mark.gpu
+
+
+def C2(x):
+    return x * (x - 1) // 2
+
+
+def gpu_tip(ctx, g, side, **kw):
+    dg = pb.DeviceGraph.from_graph(g)
+    return u64(pb.tip(ctx, dg, side, pb.make_opts(**kw) if kw else None))
+
+
+def test_tip_tiny_random(ctx):
+    for s in range(50):
+        rng = np.random.default_rng(100 + s)
+        g = synth.random_small(int(rng.integers(1, 14)), int(rng.integers(1, 10)), float(rng.choice([0.3, 0.6, 0.9])), seed=s)
+        for side in (0, 1):
+            exp = oracle.tip(g, side)
+            for P in (1, 2, 5):
+                assert np.array_equal(gpu_tip(ctx, g, side, P=P), exp), (g.name, side, P)
+
+
+@pytest.mark.parametrize("a,b", [(2, 2), (3, 5), (12, 9)])
+def test_tip_complete(ctx, a, b):
+    g = synth.complete(a, b)
+    assert (gpu_tip(ctx, g, 0) == (a - 1) * C2(b)).all()
+    assert (gpu_tip(ctx, g, 1) == (b - 1) * C2(a)).all()
+
+
+@pytest.mark.parametrize("a,b,t", [(2, 5, 4), (4, 7, 5)])
+def test_tip_clamp_closed_form(ctx, a, b, t):
+    edges = [(u, v) for u in range(a) for v in range(b)] + [(a, v) for v in range(t)]
+    g = synth.from_edges(a + 1, b, edges)
+    for P in (1, 2, 3):
+        th = gpu_tip(ctx, g, 0, P=P)
+        assert th[a] == a * C2(t)
+        assert (th[:a] == max(a * C2(t), (a - 1) * C2(b))).all()
+
+
+def test_tip_empty_and_isolated(ctx):
+    g = synth.from_edges(4, 3, [(0, 0), (3, 2)])
+    assert gpu_tip(ctx, g, 0).tolist() == [0, 0, 0, 0]
+    assert gpu_tip(ctx, g, 1).tolist() == [0, 0, 0]
+
+
+@pytest.mark.parametrize("side", [0, 1])
+def test_tip_er_small_config(ctx, side):
+    g = synth.config_graph("er_2k_1k_20k")
+    rec = golden("er_2k_1k_20k", "tip_u" if side == 0 else "tip_v")
+    res = gpu_tip(ctx, g, side, P=8)
+    check_golden(rec, res, g.digest())
+    assert np.array_equal(res, oracle.tip(g, side))
+
+
+@pytest.fixture(scope="module")
+def cl_mid():
+    g = synth.chung_lu(30000, 6000, 300000, 2.1, 4000, seed=5)
+    return g, oracle.tip(g, 0), oracle.tip(g, 1)
+
+
+@pytest.mark.parametrize("P", [0, 1, 7, 150, 1000])
+def test_tip_power_law_partitions(ctx, cl_mid, P):
+    g, eu, ev = cl_mid
+    assert np.array_equal(gpu_tip(ctx, g, 0, P=P), eu)
+    assert np.array_equal(gpu_tip(ctx, g, 1, P=P), ev)
+
+
+@pytest.mark.parametrize("flags", [pb.F_NO_DYNAMIC, pb.F_NO_BATCH, pb.F_NO_DYNAMIC | pb.F_NO_BATCH])
+def test_tip_ablation_flags(ctx, cl_mid, flags):
+    g, eu, ev = cl_mid
+    assert np.array_equal(gpu_tip(ctx, g, 0, P=40, flags=flags), eu)
+    assert np.array_equal(gpu_tip(ctx, g, 1, P=40, flags=flags), ev)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_tip_random_bounds(ctx, cl_mid, seed):
+    g, eu, ev = cl_mid
+    assert np.array_equal(gpu_tip(ctx, g, 0, P=60, bound_rule=pb.BOUND_RANDOM, seed=seed), eu)
+
+
+def test_tip_stats_and_host_buffers(ctx, cl_mid):
+    g, eu, _ = cl_mid
+    rp = np.ascontiguousarray(g.row_ptr, np.int64)
+    ci = np.ascontiguousarray(g.col_idx, np.int32)
+    out = np.zeros(g.n_u, np.uint64)
+    ctx.tip_raw(pb.host_csr(g.n_u, g.n_v, rp, ci), pb.SIDE_U, out.ctypes.data, pb.make_opts(P=150))
+    assert np.array_equal(out, eu)
+    st = ctx.stats()
+    assert st["partitions"] >= 1 and st["rho"] >= st["partitions"] - 1
+    assert st["wedges"] == st["wedges_count"] + st["wedges_cd"] + st["wedges_fd"]
+
+
+@pytest.mark.parametrize("wl,q", [("cl_500k_100k_5m", "tip_u"), ("cl_500k_100k_5m", "tip_v"),
+                                  ("cl_1m_200k_20m", "tip_u"), ("cl_1m_200k_20m", "tip_v")])
+def test_tip_full_size_golden(ctx, wl, q):
+    rec = golden(wl, q)
+    if rec is None:
+        pytest.skip("no stored oracle result")
+    g = synth.config_graph(wl)
+    res = gpu_tip(ctx, g, 0 if q == "tip_u" else 1, P=150)
+    check_golden(rec, res, g.digest())
