@@ -1,0 +1,220 @@
+#!/usr/bin/env python3
+"""Benchmark of the MI355X butterfly-peeling path.
+
+A step is one tip decomposition of both sides (U, then V) of the seeded
+Chung-Lu workload |U|=1M, |V|=200k, 20M edges, exponent 2.1, degree cap 50k,
+P=150, plain bound rule: preprocessing, priority counting, coarse-grained
+peel rounds (with recounts) and the fine-grained persistent kernel, all on the
+GPU with the graph resident in HBM before the timed region.
+
+Prints one JSON line: wedges/s over the whole step (value), the per-step
+decomposition time, the roofline of the dominant kernel class (algorithmic
+bytes / its HIP-event time on the library's stream), and the CPU oracle timed
+on a bounded sample of the same workload family.
+
+  python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload NAME]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "wedges/s + tip/wing decomposition time, learned vs plain CD bounds, 1 GPU"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    # name: (graph config, kind, P)
+    "tip_cl_1m_200k_20m": ("cl_1m_200k_20m", "tip", 150),
+    "tip_cl_500k_100k_5m": ("cl_500k_100k_5m", "tip", 150),
+    "wing_cl_500k_100k_5m": ("cl_500k_100k_5m", "wing", 400),
+    "tip_er_2k_1k_20k": ("er_2k_1k_20k", "tip", 8),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def digest(a):
+    return hashlib.sha256(np.ascontiguousarray(a, dtype="<u8").tobytes()).hexdigest()
+
+
+def golden(workload, quantity):
+    p = os.path.join(ROOT, "tests", "golden", f"{workload}__{quantity}.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        return json.load(f)
+
+
+def run_step(pb, ctx, dg, kind, P, flags):
+    """One pass of the hot path; returns (outputs, list of stats dicts)."""
+    opts = pb.make_opts(P=P, flags=flags)
+    outs, stats = [], []
+    if kind == "tip":
+        for side in (pb.SIDE_U, pb.SIDE_V):
+            outs.append(pb.tip(ctx, dg, side, opts))
+            stats.append(ctx.stats())
+    else:
+        outs.append(pb.wing(ctx, dg, opts))
+        stats.append(ctx.stats())
+    return outs, stats
+
+
+def cpu_baseline(graph_cfg, kind, budget_s):
+    """The oracle on a bounded sample: the same generator family scaled down
+    until one run takes about budget_s seconds on one host core."""
+    import oracle
+    import synth
+
+    c = dict(synth.CONFIGS[graph_cfg])
+    gen = c.pop("kind")
+    scale = 64
+    best = None
+    while scale >= 1:
+        kw = dict(c)
+        for k in ("n_u", "n_v", "m"):
+            kw[k] = max(1, int(c[k] // scale))
+        if gen == "cl":
+            kw["cap"] = max(8, c["cap"] // scale)
+        g = synth.er(**kw) if gen == "er" else synth.chung_lu(**kw)
+        t0 = time.perf_counter()
+        if kind == "tip":
+            _, st = oracle.tip(g, 0, return_stats=True)
+            # counting walks the same wedges as peeling without graph updates
+            wedges = 2 * st["wedges"]
+        else:
+            _, st = oracle.wing(g, return_stats=True)
+            wedges = st["wedges"]
+        dt = time.perf_counter() - t0
+        best = dict(value=wedges / dt if dt > 0 else 0.0, unit="wedges/s", cores=1, kind="oracle",
+                    sample=f"{g.name}: {kind} side U by sequential bottom-up peeling, {wedges} wedges in {dt:.2f} s "
+                           f"(workload scaled 1/{scale})", seconds=round(dt, 2))
+        if dt * 4 > budget_s or scale == 1:
+            break
+        scale //= 2
+    return best
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="tip_cl_1m_200k_20m", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for the CPU baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2110_12511_amd as pb
+    import synth
+
+    graph_cfg, kind, P = WORKLOADS[args.workload]
+    log(f"[bench] generating {graph_cfg}")
+    g = synth.config_graph(graph_cfg)
+    log(f"[bench] graph {g.name}: m={g.m}")
+    ctx = pb.Context()
+    dg = pb.DeviceGraph.from_graph(g)
+    torch.cuda.synchronize()
+
+    for i in range(args.warmup):
+        run_step(pb, ctx, dg, kind, P, 0)
+        torch.cuda.synchronize()
+        log(f"[bench] warmup {i + 1}/{args.warmup} done")
+
+    step_ms, all_stats, outs = [], [], None
+    torch.cuda.synchronize()
+    t_all = time.perf_counter()
+    for i in range(args.steps):
+        t0 = time.perf_counter()
+        outs, stats = run_step(pb, ctx, dg, kind, P, pb.binding.F_KERNEL_TIMING)
+        torch.cuda.synchronize()
+        step_ms.append((time.perf_counter() - t0) * 1e3)
+        all_stats.append(stats)
+        log(f"[bench] step {i + 1}/{args.steps}: {step_ms[-1]:.1f} ms")
+    torch.cuda.synchronize()
+    total_s = time.perf_counter() - t_all
+
+    wedges_per_step = [sum(s["wedges"] for s in st) for st in all_stats]
+    value = sum(wedges_per_step) / total_s
+    ms_per_step = total_s * 1e3 / args.steps
+
+    # dominant kernel class over the timed steps
+    agg = {}
+    for st in all_stats:
+        for s in st:
+            for name, k in s["kstat"].items():
+                a = agg.setdefault(name, dict(ms=0.0, launches=0, bytes=0, wedges=0))
+                for f in a:
+                    a[f] += k[f]
+    dom = max(agg, key=lambda n: agg[n]["ms"])
+    d = agg[dom]
+    achieved = d["bytes"] / (d["ms"] / 1e3) / 1e9 if d["ms"] > 0 else 0.0
+    roofline = dict(bound="hbm", kernel=dom, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                    avg_launch_ms=round(d["ms"] / max(d["launches"], 1), 4), launches=d["launches"],
+                    algorithmic_bytes=d["bytes"], wedges=d["wedges"],
+                    kernel_wedges_per_s=round(d["wedges"] / (d["ms"] / 1e3), 1) if d["ms"] > 0 else 0.0)
+
+    # parity evidence against stored oracle results (when present)
+    parity = {}
+    qnames = ["tip_u", "tip_v"] if kind == "tip" else ["wing"]
+    for q, t in zip(qnames, outs):
+        rec = golden(graph_cfg, q)
+        if rec is not None:
+            parity[q] = digest(pb.to_numpy_u64(t)) == rec["sha256"]
+
+    last = all_stats[-1]
+    phases = [{k: round(s[k], 2) for k in ("ms_total", "ms_prep", "ms_count", "ms_cd", "ms_fd_prep", "ms_fd")}
+              for s in last]
+    work = [{k: s[k] for k in ("wedges", "wedges_count", "wedges_cd", "wedges_fd", "rho", "recounts", "partitions",
+                                "P_used", "fd_work_max", "fd_work_sum", "updates", "links", "blooms")} for s in last]
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on a bounded sample")
+        cpu = cpu_baseline(graph_cfg, kind, args.cpu_budget)
+
+    line = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "wedges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": f"{kind} decomposition ({'both sides' if kind == 'tip' else 'all edges'}) of {g.name}",
+                   "graph": graph_cfg, "P": P, "bound_rule": "plain", "m": g.m, "n_u": g.n_u, "n_v": g.n_v},
+        "decomposition_ms": round(min(step_ms), 2),
+        "phases_ms": phases,
+        "work": work,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "parity_vs_oracle": parity or None,
+    }
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

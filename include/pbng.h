@@ -85,6 +85,25 @@ typedef enum {
                                    instead of bloom-aggregated batches
                                    (Section 5.1)                            */
 #define PBNG_F_NO_DENSE_TILE 0x4 /* counting: scalar path for hub pairs too */
+#define PBNG_F_KERNEL_TIMING 0x8 /* time kernel classes with HIP events on the
+                                    context stream (fills pbng_stats.kstat) */
+
+/* Kernel classes timed under PBNG_F_KERNEL_TIMING. */
+enum {
+    PBNG_K_COUNT = 0,   /* wedge-traversal counting / recounting            */
+    PBNG_K_TIP_PEEL = 1,/* coarse-grained tip peel rounds                   */
+    PBNG_K_FD = 2,      /* fine-grained (per-partition) peeling             */
+    PBNG_K_WING_CD = 3, /* coarse-grained wing batch updates                */
+    PBNG_K_DENSE = 4,   /* int8 matrix-core hub tiles                       */
+    PBNG_K_NCLASS = 5
+};
+
+typedef struct {
+    double ms;          /* summed event time of the class's launches         */
+    uint64_t launches;  /* timed intervals (one per round / pass)            */
+    uint64_t bytes;     /* algorithmic bytes the method moves in them        */
+    uint64_t wedges;    /* wedges (or links) walked in them                  */
+} pbng_kernel_stat;
 
 typedef struct {
     int32_t P;          /* partitions; 0 = default (tip 150; wing 400 below
@@ -115,6 +134,7 @@ typedef struct {
     int32_t P_used;           /* partitions requested after clamping         */
     uint64_t fd_work_max, fd_work_sum; /* estimated fine-grained work        */
     uint64_t dense_pairs;     /* hub pairs counted on matrix cores           */
+    pbng_kernel_stat kstat[PBNG_K_NCLASS];
 } pbng_stats;
 
 /* Create a context bound to the current HIP device and the given stream

@@ -58,6 +58,20 @@ class Opts(ctypes.Structure):
     ]
 
 
+K_COUNT, K_TIP_PEEL, K_FD, K_WING_CD, K_DENSE, K_NCLASS = 0, 1, 2, 3, 4, 5
+K_NAMES = ["count", "tip_peel", "fd", "wing_cd", "dense"]
+F_KERNEL_TIMING = 0x8
+
+
+class KernelStat(ctypes.Structure):
+    _fields_ = [
+        ("ms", ctypes.c_double),
+        ("launches", ctypes.c_uint64),
+        ("bytes", ctypes.c_uint64),
+        ("wedges", ctypes.c_uint64),
+    ]
+
+
 class Stats(ctypes.Structure):
     _fields_ = [
         ("ms_total", ctypes.c_double),
@@ -81,10 +95,17 @@ class Stats(ctypes.Structure):
         ("fd_work_max", ctypes.c_uint64),
         ("fd_work_sum", ctypes.c_uint64),
         ("dense_pairs", ctypes.c_uint64),
+        ("kstat", KernelStat * K_NCLASS),
     ]
 
     def as_dict(self):
-        return {name: getattr(self, name) for name, _ in self._fields_}
+        d = {name: getattr(self, name) for name, _ in self._fields_ if name != "kstat"}
+        d["kstat"] = {
+            K_NAMES[i]: dict(ms=self.kstat[i].ms, launches=self.kstat[i].launches, bytes=self.kstat[i].bytes,
+                             wedges=self.kstat[i].wedges)
+            for i in range(K_NCLASS)
+        }
+        return d
 
 
 EXPORTS = ["pbng_create", "pbng_destroy", "pbng_last_error", "pbng_last_stats", "pbng_count", "pbng_tip", "pbng_wing"]

@@ -58,7 +58,9 @@ struct CountArgs {
     u32 *dntouch;                // [slots]
     i64 n;
     u64 *wedges;                 // wedges walked
+    KCounters *kc;               // algorithmic-work counters of this class
 };
+
 
 // ------------------------------------------------------------------ traversal
 
@@ -114,8 +116,12 @@ __device__ __forceinline__ void for_each_wedge(const CountArgs &a, i32 s, const 
 // Everything done for one start: pass 1 (wedge counts), the per-bloom
 // epilogue, pass 2 (mid and edge contributions, twin pairs).
 template <int BLOCK, int MODE, class Acc>
-__device__ __forceinline__ void process_start(const CountArgs &a, i32 s, Acc &A, const ChunkSmem &sm, u64 &wedges) {
-    for_each_wedge<BLOCK>(a, s, sm, [&](int, i64, i32 last, i64) { A.add(last); ++wedges; }, [&](i64) {});
+__device__ __forceinline__ void process_start(const CountArgs &a, i32 s, Acc &A, const ChunkSmem &sm, Tally &t) {
+    for_each_wedge<BLOCK>(a, s, sm, [&](int, i64, i32 last, i64) { A.add(last); ++t.wedges; }, [&](i64) {});
+    if (threadIdx.x == 0) {
+        t.segments += (u64)(a.loff[s + 1] - a.loff[s]);
+        t.items += 1;
+    }
 
     if (threadIdx.x == 0) sm.bcast[0] = A.entries();
     __syncthreads();
@@ -162,6 +168,7 @@ __device__ __forceinline__ void process_start(const CountArgs &a, i32 s, Acc &A,
             if (MODE & M_VERTEX) {
                 my_start += b;
                 atomicAdd((unsigned long long *)&a.sup_label[key], (unsigned long long)b);
+                ++t.atomics;
             }
             if (MODE & M_BE_SIZE) {
                 my_blooms += 1;
@@ -169,8 +176,11 @@ __device__ __forceinline__ void process_start(const CountArgs &a, i32 s, Acc &A,
             }
         }
         if (MODE & M_VERTEX) {
-            u64 t = block_sum_u64<BLOCK>(my_start, sm.red);
-            if (threadIdx.x == 0 && t) atomicAdd((unsigned long long *)&a.sup_label[s], (unsigned long long)t);
+            u64 tt = block_sum_u64<BLOCK>(my_start, sm.red);
+            if (threadIdx.x == 0 && tt) {
+                atomicAdd((unsigned long long *)&a.sup_label[s], (unsigned long long)tt);
+                ++t.atomics;
+            }
         }
         if (MODE & M_BE_SIZE) {
             u64 tb = block_sum_u64<BLOCK>(my_blooms, sm.red);
@@ -205,16 +215,23 @@ __device__ __forceinline__ void process_start(const CountArgs &a, i32 s, Acc &A,
                     if (cc < 2) return;
                 }
                 atomicAdd((unsigned long long *)&sm.agg[seg], (unsigned long long)(cc - 1));
-                if (MODE & (M_EDGE | M_BE_FILL))
+                if (MODE & (M_EDGE | M_BE_FILL)) {
                     atomicAdd((unsigned long long *)&a.sup_edge[a.leid[pos]], (unsigned long long)(cc - 1));
+                    ++t.atomics;
+                }
             },
             [&](i64 cb) {
                 u64 g = sm.agg[threadIdx.x];
                 if (g) {
                     i64 j = cb + threadIdx.x;
-                    if (MODE & M_VERTEX) atomicAdd((unsigned long long *)&a.sup_label[a.ladj[j]], (unsigned long long)g);
-                    if (MODE & (M_EDGE | M_BE_FILL))
+                    if (MODE & M_VERTEX) {
+                        atomicAdd((unsigned long long *)&a.sup_label[a.ladj[j]], (unsigned long long)g);
+                        ++t.atomics;
+                    }
+                    if (MODE & (M_EDGE | M_BE_FILL)) {
                         atomicAdd((unsigned long long *)&a.sup_edge[a.leid[j]], (unsigned long long)g);
+                        ++t.atomics;
+                    }
                     sm.agg[threadIdx.x] = 0;
                 }
             });
@@ -241,7 +258,7 @@ __global__ __launch_bounds__(BLOCK) void k_count_hash(CountArgs a) {
     A.keys = s_keys;
     A.vals = s_vals;
     A.bids = s_bids;
-    u64 wedges = 0;
+    Tally tl;
     for (;;) {
         if (threadIdx.x == 0) s_item = (i32)atomicAdd(a.next, 1u);
         __syncthreads();
@@ -255,10 +272,10 @@ __global__ __launch_bounds__(BLOCK) void k_count_hash(CountArgs a) {
         while ((i64(1) << logcap) < 2 * ws && logcap < LOGCAP) ++logcap;
         A.init(logcap, threadIdx.x, BLOCK);
         __syncthreads();
-        process_start<BLOCK, MODE>(a, s, A, sm, wedges);
+        process_start<BLOCK, MODE>(a, s, A, sm, tl);
         __syncthreads();
     }
-    if (wedges) atomicAdd((unsigned long long *)a.wedges, (unsigned long long)wedges);
+    tl.flush(a.kc, a.wedges);
 }
 
 template <int MODE>
@@ -277,7 +294,7 @@ __global__ __launch_bounds__(256) void k_count_dense(CountArgs a) {
     A.bids = a.dbid ? a.dbid + (i64)blockIdx.x * a.n : nullptr;
     A.touch = a.dtouch + (i64)blockIdx.x * a.n;
     A.ntouch = a.dntouch + blockIdx.x;
-    u64 wedges = 0;
+    Tally tl;
     for (;;) {
         if (threadIdx.x == 0) s_item = (i32)atomicAdd(a.next, 1u);
         __syncthreads();
@@ -285,11 +302,11 @@ __global__ __launch_bounds__(256) void k_count_dense(CountArgs a) {
         __syncthreads();
         if (item >= a.nstarts) break;
         const i32 s = a.starts[item];
-        process_start<BLOCK, MODE>(a, s, A, sm, wedges);
+        process_start<BLOCK, MODE>(a, s, A, sm, tl);
         __syncthreads();
         A.reset(threadIdx.x, BLOCK);
     }
-    if (wedges) atomicAdd((unsigned long long *)a.wedges, (unsigned long long)wedges);
+    tl.flush(a.kc, a.wedges);
 }
 
 // ------------------------------------------------------------------ binning
@@ -337,15 +354,19 @@ template <int MODE>
 static void launch_all(Ctx &c, const DevGraph &G, CountArgs a, const Bins &b) {
     u32 *next = c.alloc<u32>(3);
     PBNG_HIP(hipMemsetAsync(next, 0, 3 * sizeof(u32), c.stream));
-    // large starts first: they are the long tail
+    a.kc = c.kctr + PBNG_K_COUNT;
+    const int slots = (int)std::min<i64>(b.cnt[2], (i64)c.num_cu);
     if (b.cnt[2]) {
-        int slots = (int)std::min<i64>(b.cnt[2], (i64)c.num_cu);
         a.dcnt = c.alloc<u32>((i64)slots * G.n);
         a.dtouch = c.alloc<i32>((i64)slots * G.n);
         a.dbid = (MODE & M_BE_FILL) ? c.alloc<i32>((i64)slots * G.n) : nullptr;
         a.dntouch = c.alloc<u32>(slots);
         PBNG_HIP(hipMemsetAsync(a.dcnt, 0, sizeof(u32) * slots * G.n, c.stream));
         PBNG_HIP(hipMemsetAsync(a.dntouch, 0, sizeof(u32) * slots, c.stream));
+    }
+    c.kbegin(PBNG_K_COUNT);
+    // large starts first: they are the long tail
+    if (b.cnt[2]) {
         a.starts = b.lists + 2 * G.n;
         a.nstarts = b.cnt[2];
         a.next = next + 2;
@@ -368,6 +389,7 @@ static void launch_all(Ctx &c, const DevGraph &G, CountArgs a, const Bins &b) {
         hipLaunchKernelGGL((k_count_hash<64, 10, MODE>), dim3(grid), dim3(64), 0, c.stream, a);
         PBNG_LAUNCH_CHECK();
     }
+    c.kend(PBNG_K_COUNT);
 }
 
 static CountArgs base_args(const DevGraph &G) {

@@ -27,6 +27,20 @@ __device__ __forceinline__ void st_coherent(T *p, T v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Per-thread tallies of algorithmic work, flushed once per workgroup.
+struct Tally {
+    u64 wedges = 0, segments = 0, atomics = 0, items = 0;
+    __device__ void flush(KCounters *kc, u64 *wedges_out) {
+        if (wedges) {
+            if (wedges_out) atomicAdd((unsigned long long *)wedges_out, (unsigned long long)wedges);
+            if (kc) atomicAdd((unsigned long long *)&kc->wedges, (unsigned long long)wedges);
+        }
+        if (kc && segments) atomicAdd((unsigned long long *)&kc->segments, (unsigned long long)segments);
+        if (kc && atomics) atomicAdd((unsigned long long *)&kc->atomics, (unsigned long long)atomics);
+        if (kc && items) atomicAdd((unsigned long long *)&kc->items, (unsigned long long)items);
+    }
+};
+
 __device__ __forceinline__ u32 hash32(u32 x) { return x * 2654435761u; }
 
 template <int BLOCK>

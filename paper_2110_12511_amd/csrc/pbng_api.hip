@@ -19,6 +19,7 @@ struct CallScope {
     explicit CallScope(Ctx &cc) : c(cc) { c.stats = pbng_stats{}; }
     ~CallScope() {
         (void)hipStreamSynchronize(c.stream);
+        c.timing = false;
         c.arena.release_all();
     }
 };
@@ -129,6 +130,8 @@ void pbng_destroy(pbng_ctx *x) {
     (void)hipStreamSynchronize(x->c.stream);
     x->c.arena.destroy();
     if (x->c.sel_scratch) (void)hipFree(x->c.sel_scratch);
+    if (x->c.kctr) (void)hipFree(x->c.kctr);
+    for (hipEvent_t e : x->c.ev_pool) (void)hipEventDestroy(e);
     delete x;
 }
 
@@ -153,6 +156,7 @@ int pbng_count(pbng_ctx *x, const pbng_csr *g, pbng_count_kind kind, const pbng_
     pbng_opts o = default_opts(opts);
     return guarded(c, [&] {
         auto t0 = std::chrono::steady_clock::now();
+        c.timing_begin_call((o.flags & PBNG_F_KERNEL_TIMING) != 0);
         pbng_csr dg = device_graph(c, *g);
         OutBuf ob(c, out, nout, !g->on_device);
         DevGraph G;
@@ -172,6 +176,7 @@ int pbng_count(pbng_ctx *x, const pbng_csr *g, pbng_count_kind kind, const pbng_
         }
         ob.finish();
         c.stats.ms_count = ms_since(t1);
+        if (o.flags & PBNG_F_KERNEL_TIMING) c.timing_end_call();
         c.stats.ms_total = ms_since(t0);
     });
 }
@@ -188,6 +193,7 @@ int pbng_tip(pbng_ctx *x, const pbng_csr *g, pbng_side side, const pbng_opts *op
     pbng_opts o = default_opts(opts);
     return guarded(c, [&] {
         auto t0 = std::chrono::steady_clock::now();
+        c.timing_begin_call((o.flags & PBNG_F_KERNEL_TIMING) != 0);
         pbng_csr dg = device_graph(c, *g);
         OutBuf ob(c, tip_out, nout, !g->on_device);
         DevGraph G;
@@ -196,6 +202,7 @@ int pbng_tip(pbng_ctx *x, const pbng_csr *g, pbng_side side, const pbng_opts *op
         c.stats.ms_prep = ms_since(t0);
         tip_decompose(c, G, side, o, ob.dev);
         ob.finish();
+        if (o.flags & PBNG_F_KERNEL_TIMING) c.timing_end_call();
         c.stats.ms_total = ms_since(t0);
     });
 }
@@ -210,6 +217,7 @@ int pbng_wing(pbng_ctx *x, const pbng_csr *g, const pbng_opts *opts, uint64_t *w
     pbng_opts o = default_opts(opts);
     return guarded(c, [&] {
         auto t0 = std::chrono::steady_clock::now();
+        c.timing_begin_call((o.flags & PBNG_F_KERNEL_TIMING) != 0);
         pbng_csr dg = device_graph(c, *g);
         OutBuf ob(c, wing_out, g->m, !g->on_device);
         DevGraph G;
@@ -218,6 +226,7 @@ int pbng_wing(pbng_ctx *x, const pbng_csr *g, const pbng_opts *opts, uint64_t *w
         c.stats.ms_prep = ms_since(t0);
         wing_decompose(c, G, o, ob.dev);
         ob.finish();
+        if (o.flags & PBNG_F_KERNEL_TIMING) c.timing_end_call();
         c.stats.ms_total = ms_since(t0);
     });
 }

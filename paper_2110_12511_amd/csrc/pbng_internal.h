@@ -49,6 +49,12 @@ struct Arena {
     void destroy();      // hipFree everything
 };
 
+// Algorithmic-work counters a traversal kernel adds to (one set per kernel
+// class): wedges walked, list segments opened, 64-bit atomic updates.
+struct KCounters {
+    u64 wedges, segments, atomics, items;
+};
+
 struct Ctx {
     hipStream_t stream = nullptr;
     int device = 0;
@@ -58,10 +64,21 @@ struct Ctx {
     pbng_stats stats{};
     // device scratch of the range selection, kept for the context's life
     void *sel_scratch = nullptr;
+    // kernel-class timing (PBNG_F_KERNEL_TIMING)
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_next = 0;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> intervals[PBNG_K_NCLASS];
+    KCounters *kctr = nullptr;  // device [PBNG_K_NCLASS], zeroed per call
     template <class T>
     T *alloc(size_t n) {
         return static_cast<T *>(arena.take((n ? n : 1) * sizeof(T)));
     }
+    hipEvent_t event();
+    void kbegin(int cls);
+    void kend(int cls);
+    void timing_begin_call(bool on);
+    void timing_end_call();  // fills stats.kstat (synchronises)
 };
 
 // Graph in device memory after preprocessing (Algorithm 1, priority

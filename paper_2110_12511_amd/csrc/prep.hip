@@ -54,14 +54,16 @@ __global__ void k_vdeg64(i64 n_u, i64 n_v, const i32 *deg, i64 *vdeg) {
     for (i64 v = blockIdx.x * (i64)blockDim.x + threadIdx.x; v < n_v; v += (i64)gridDim.x * blockDim.x) vdeg[v] = deg[n_u + v];
 }
 
-__global__ void k_vfill(i64 n_u, i64 m, const i64 *row, const i32 *col, i64 *cursor, i32 *vadj, i32 *veid) {
-    // V lists come out in arbitrary order, which the peeling ignores
+__global__ void k_vkeys(i64 m, const i32 *col, u64 *keys, i32 *vals) {
     for (i64 e = blockIdx.x * (i64)blockDim.x + threadIdx.x; e < m; e += (i64)gridDim.x * blockDim.x) {
-        i64 u = row_of(row, n_u, e);
-        i64 p = atomicAdd((unsigned long long *)&cursor[col[e]], 1ull);
-        vadj[p] = (i32)u;
-        veid[p] = (i32)e;
+        keys[e] = (u64)col[e];
+        vals[e] = (i32)e;
     }
+}
+
+__global__ void k_vscatter(i64 n_u, i64 m, const i64 *row, const i32 *veid, i32 *vadj) {
+    for (i64 p = blockIdx.x * (i64)blockDim.x + threadIdx.x; p < m; p += (i64)gridDim.x * blockDim.x)
+        vadj[p] = (i32)row_of(row, n_u, veid[p]);
 }
 
 __global__ void k_deg_keys(const i32 *deg, i64 n, i32 maxdeg, u64 *keys) {
@@ -161,12 +163,19 @@ void build_graph(Ctx &c, const pbng_csr &g, DevGraph &G) {
     }
     exclusive_scan<i64>(c, vdeg, G.vrow, n_v);
     G.vadj = c.alloc<i32>(m);
-    G.veid = c.alloc<i32>(m);
-    i64 *cursor = c.alloc<i64>(n_v);
-    if (n_v) PBNG_HIP(hipMemcpyAsync(cursor, G.vrow, sizeof(i64) * n_v, hipMemcpyDeviceToDevice, s));
     if (m) {
-        hipLaunchKernelGGL(k_vfill, dim3(gridN(m)), dim3(256), 0, s, n_u, m, G.urow, G.ucol, cursor, G.vadj, G.veid);
+        // stable sort of edge ids by V id: every V list comes out in
+        // increasing U id (the U-side CSR is u-major)
+        u64 *vk = c.alloc<u64>(m);
+        i32 *ve = c.alloc<i32>(m);
+        hipLaunchKernelGGL(k_vkeys, dim3(gridN(m)), dim3(256), 0, s, m, G.ucol, vk, ve);
         PBNG_LAUNCH_CHECK();
+        u64 *svk;
+        radix_sort_u64(c, vk, ve, m, bits_for((u64)(n_v > 0 ? n_v - 1 : 0)), &svk, &G.veid);
+        hipLaunchKernelGGL(k_vscatter, dim3(gridN(m)), dim3(256), 0, s, n_u, m, G.urow, (const i32 *)G.veid, G.vadj);
+        PBNG_LAUNCH_CHECK();
+    } else {
+        G.veid = c.alloc<i32>(1);
     }
 
     // labels: stable sort of global ids by decreasing degree

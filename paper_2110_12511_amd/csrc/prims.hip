@@ -49,6 +49,67 @@ void Arena::destroy() {
     bytes_held = 0;
 }
 
+// ------------------------------------------------------------------ kernel timing
+
+hipEvent_t Ctx::event() {
+    if (ev_next == ev_pool.size()) {
+        hipEvent_t e;
+        PBNG_HIP(hipEventCreate(&e));
+        ev_pool.push_back(e);
+    }
+    return ev_pool[ev_next++];
+}
+
+void Ctx::kbegin(int cls) {
+    if (!timing) return;
+    hipEvent_t a = event(), b = event();
+    PBNG_HIP(hipEventRecord(a, stream));
+    intervals[cls].push_back({a, b});
+}
+
+void Ctx::kend(int cls) {
+    if (!timing) return;
+    PBNG_HIP(hipEventRecord(intervals[cls].back().second, stream));
+}
+
+void Ctx::timing_begin_call(bool on) {
+    timing = on;
+    ev_next = 0;
+    for (auto &v : intervals) v.clear();
+    if (!kctr) PBNG_HIP(hipMalloc(&kctr, sizeof(KCounters) * PBNG_K_NCLASS));
+    PBNG_HIP(hipMemsetAsync(kctr, 0, sizeof(KCounters) * PBNG_K_NCLASS, stream));
+}
+
+// Algorithmic bytes per unit of work:
+//   traversal kernels: 4 B per wedge (the id of its far end), 12 B per list
+//   segment (the middle vertex's id and its offset pair), 16 B per 64-bit
+//   atomic update (read-modify-write), 16 B per item (its offsets and
+//   support);
+//   wing batch updates: 8 B per link walked (bloom id and twin), 16 B per
+//   atomic support update, 16 B per bloom touched (bloom number, count and
+//   offsets).
+void Ctx::timing_end_call() {
+    PBNG_HIP(hipStreamSynchronize(stream));
+    KCounters h[PBNG_K_NCLASS];
+    PBNG_HIP(hipMemcpy(h, kctr, sizeof(h), hipMemcpyDeviceToHost));
+    for (int k = 0; k < PBNG_K_NCLASS; ++k) {
+        pbng_kernel_stat &s = stats.kstat[k];
+        s.ms = 0;
+        s.launches = intervals[k].size();
+        for (auto &iv : intervals[k]) {
+            float ms = 0;
+            PBNG_HIP(hipEventElapsedTime(&ms, iv.first, iv.second));
+            s.ms += ms;
+        }
+        s.wedges = h[k].wedges;
+        if (k == PBNG_K_WING_CD)
+            s.bytes = 8 * h[k].wedges + 16 * h[k].atomics + 16 * h[k].segments + 16 * h[k].items;
+        else
+            s.bytes = 4 * h[k].wedges + 12 * h[k].segments + 16 * h[k].atomics + 16 * h[k].items;
+    }
+    timing = false;
+}
+
 // ------------------------------------------------------------------ small kernels
 
 template <class T>

@@ -24,6 +24,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 
 #include "dev_common.h"
 #include "pbng_internal.h"
@@ -42,14 +44,26 @@ struct TipCtl {
     double scale;   // scaling factor for the next target
     u32 nF;         // current active-set size
     u32 nF2;        // next active-set size
-    u64 wF;         // wedges of the current active set
-    u64 wF2;        // wedges of the next active set
+    u64 wF;         // wedges of the current active set (live lists)
     u64 wedges;     // wedges walked by peeling kernels
-    u32 nbin[3];    // active-set bins
-    u32 next[3];    // work counters
+    u32 nbin[4];    // active-set bins: small, medium, tiled, dense
+    u32 next[4];    // work counters
     u32 ndirty;     // Y lists to compact
+    u32 nyt;        // pull rounds: Y vertices touched by the active set
+    u32 nrecv;      // pull rounds: receivers
     u32 pad;
+    u64 pw;         // pull rounds: receiver wedges
 };
+
+// Active sets at least this large may be peeled from the receiving side
+// (off by default: on the power-law workloads measured so far the key-tile
+// path is faster; PBNG_PULL_MIN_F turns it on for tuning).
+constexpr u32 PULL_MIN_F = 0xFFFFFFFFu;
+
+// Heavy active vertices accumulate c(x, x') in LDS over key tiles of
+// 2^TILE_LOG consecutive X ids, two 16-bit counters per 32-bit word.
+constexpr int TILE_LOG = 16;
+constexpr i64 TB_LIMIT = i64(1) << 20;  // tile-boundary scratch per workgroup (ints)
 
 struct PeelArgs {
     const i64 *xrow;
@@ -62,15 +76,19 @@ struct PeelArgs {
     u32 *next;
     const unsigned char *st;
     u64 *sup;
-    u64 *w;
+    const u64 *wi;       // wedges of each active vertex over the live lists
     const u64 *bound;
     i32 *nf;
     u32 *nnf;
     u32 *dcnt;
     i32 *dtouch;
     u32 *dntouch;
+    i32 *tbnd;           // tiled path: per-workgroup tile boundaries
+    i64 tbnd_stride;
+    i32 ntiles;
     i64 nx;
     u64 *wedges;
+    KCounters *kc;
 };
 
 struct ItemSmem {
@@ -81,13 +99,18 @@ struct ItemSmem {
     i64 *bcast;
 };
 
-// Every wedge x -> y -> x' of an active x over the live Y lists; x' must be
-// alive.  Then for every touched x': its work loses c (one wedge per shared
-// y), and its support loses C(c, 2); a support that crosses below the bound
-// puts x' in the next active set (exactly once: supports only decrease).
+// Every wedge x -> y -> x' of an active x over the live Y lists is counted
+// per x'; then every alive x' with c >= 2 loses C(c, 2) of its support, and
+// a support that crosses below the bound puts x' in the next active set
+// (exactly once: supports only decrease).  Keys that are not alive (other
+// active vertices) are dropped in that epilogue, once per key.
 template <int BLOCK, class Acc>
-__device__ __forceinline__ void peel_item(const PeelArgs &a, i32 x, Acc &A, const ItemSmem &sm, u64 &wedges) {
+__device__ __forceinline__ void peel_item(const PeelArgs &a, i32 x, Acc &A, const ItemSmem &sm, Tally &t) {
     const i64 jb = a.xrow[x], je = a.xrow[x + 1];
+    if (threadIdx.x == 0) {
+        t.segments += (u64)(je - jb);
+        t.items += 1;
+    }
     for (i64 cb = jb; cb < je; cb += BLOCK) {
         i64 j = cb + threadIdx.x;
         i32 pl = 0;
@@ -111,8 +134,7 @@ __device__ __forceinline__ void peel_item(const PeelArgs &a, i32 x, Acc &A, cons
             i32 before = lo ? sm.pre[lo - 1] : 0;
             i32 xp = a.yadj[sm.moff[lo] + (k - before)];
             if (xp == x) continue;
-            ++wedges;
-            if (a.st[xp] != ST_ALIVE) continue;
+            ++t.wedges;
             A.add(xp);
         }
         __syncthreads();
@@ -126,12 +148,12 @@ __device__ __forceinline__ void peel_item(const PeelArgs &a, i32 x, Acc &A, cons
         i32 key;
         u32 c32;
         A.entry(i, key, c32);
-        if (key < 0 || c32 == 0) continue;
+        if (key < 0 || c32 < 2) continue;
+        if (a.st[key] != ST_ALIVE) continue;
         u64 cc = c32;
-        atomicAdd((unsigned long long *)&a.w[key], (unsigned long long)(0ull - cc));
-        if (cc < 2) continue;
         u64 d = cc * (cc - 1) / 2;
         u64 old = atomicAdd((unsigned long long *)&a.sup[key], (unsigned long long)(0ull - d));
+        ++t.atomics;
         if (old >= B && old - d < B) {
             u32 p = atomicAdd(a.nnf, 1u);
             a.nf[p] = key;
@@ -157,7 +179,7 @@ __global__ __launch_bounds__(BLOCK) void k_tip_peel_hash(PeelArgs a, int bin) {
     A.vals = s_vals;
     A.bids = nullptr;
     const u32 n = a.nitems[bin];
-    u64 wedges = 0;
+    Tally tl;
     for (;;) {
         if (threadIdx.x == 0) s_item = (i32)atomicAdd(&a.next[bin], 1u);
         __syncthreads();
@@ -165,14 +187,14 @@ __global__ __launch_bounds__(BLOCK) void k_tip_peel_hash(PeelArgs a, int bin) {
         __syncthreads();
         if ((u32)item >= n) break;
         const i32 x = a.items[item];
-        const i64 wx = (i64)a.w[x];
+        const i64 wx = (i64)a.wi[x];
         int logcap = 6;
         while ((i64(1) << logcap) < 2 * wx && logcap < LOGCAP) ++logcap;
         A.init(logcap, threadIdx.x, BLOCK);
         __syncthreads();
-        peel_item<BLOCK>(a, x, A, sm, wedges);
+        peel_item<BLOCK>(a, x, A, sm, tl);
     }
-    if (wedges) atomicAdd((unsigned long long *)a.wedges, (unsigned long long)wedges);
+    tl.flush(a.kc, a.wedges);
 }
 
 __global__ __launch_bounds__(256) void k_tip_peel_dense(PeelArgs a, int bin) {
@@ -190,29 +212,510 @@ __global__ __launch_bounds__(256) void k_tip_peel_dense(PeelArgs a, int bin) {
     A.touch = a.dtouch + (i64)blockIdx.x * a.nx;
     A.ntouch = a.dntouch + blockIdx.x;
     const u32 n = a.nitems[bin];
-    u64 wedges = 0;
+    Tally tl;
     for (;;) {
         if (threadIdx.x == 0) s_item = (i32)atomicAdd(&a.next[bin], 1u);
         __syncthreads();
         const i32 item = s_item;
         __syncthreads();
         if ((u32)item >= n) break;
-        peel_item<BLOCK>(a, a.items[item], A, sm, wedges);
+        peel_item<BLOCK>(a, a.items[item], A, sm, tl);
         A.reset(threadIdx.x, BLOCK);
     }
-    if (wedges) atomicAdd((unsigned long long *)a.wedges, (unsigned long long)wedges);
+    tl.flush(a.kc, a.wedges);
+}
+
+// Heavy active vertices: the live Y lists are sorted by X id, so the wedges
+// of x whose far end lies in a key tile [r0, r0 + 2^TILE_LOG) form one run of
+// every list.  The run boundaries of all (neighbour, tile) pairs are found
+// once per vertex by binary search; then tile by tile the wedges are counted
+// in LDS (two 16-bit counters per word; a count never exceeds d_x < 2^16),
+// and the tile's counters are scanned for c >= 2.  No global atomic is issued
+// per wedge.
+template <int TLOG>
+__global__ __launch_bounds__(512) void k_tip_peel_tiled(PeelArgs a, int bin) {
+    constexpr int BLOCK = 512;
+    constexpr int WORDS = (1 << TLOG) / 2;
+    __shared__ u32 cnt[WORDS];
+    __shared__ i32 s_pre[BLOCK];
+    __shared__ i64 s_moff[BLOCK];
+    __shared__ i32 s_wave[BLOCK / WAVE];
+    __shared__ i32 s_item;
+    for (int i = threadIdx.x; i < WORDS; i += BLOCK) cnt[i] = 0;
+    i32 *bnd = a.tbnd + (i64)blockIdx.x * a.tbnd_stride;
+    const u32 n = a.nitems[bin];
+    const i32 nt = a.ntiles;
+    const u64 B = *a.bound;
+    Tally tl;
+    __syncthreads();
+    for (;;) {
+        if (threadIdx.x == 0) s_item = (i32)atomicAdd(&a.next[bin], 1u);
+        __syncthreads();
+        const i32 item = s_item;
+        __syncthreads();
+        if ((u32)item >= n) break;
+        const i32 x = a.items[item];
+        const i64 jb = a.xrow[x];
+        const i32 d = (i32)(a.xrow[x + 1] - jb);
+        if (threadIdx.x == 0) {
+            tl.segments += (u64)d;
+            tl.items += 1;
+        }
+        // run boundaries: bnd[j * (nt + 1) + t] = first entry of list j with key >= t * 2^TLOG
+        const i32 nb = d * (nt + 1);
+        for (i32 q = threadIdx.x; q < nb; q += BLOCK) {
+            const i32 j = q / (nt + 1), t = q - j * (nt + 1);
+            const i32 y = a.xadj[jb + j];
+            const i64 base = a.yrow[y];
+            i64 lo = base, hi = base + a.ylen[y];
+            i64 r = (i64)t << TLOG;
+            if (r > a.nx) r = a.nx;
+            while (lo < hi) {
+                i64 md = (lo + hi) >> 1;
+                if ((i64)a.yadj[md] < r) lo = md + 1; else hi = md;
+            }
+            st_coherent(&bnd[q], (i32)(lo - base));
+        }
+        __syncthreads();
+        for (i32 t = 0; t < nt; ++t) {
+            const i32 r0 = t << TLOG;
+            bool any = false;
+            for (i32 cb = 0; cb < d; cb += BLOCK) {
+                const i32 j = cb + threadIdx.x;
+                i32 pl = 0;
+                i64 moff = 0;
+                if (j < d) {
+                    const i32 y = a.xadj[jb + j];
+                    const i32 b0 = ld_coherent(&bnd[j * (nt + 1) + t]);
+                    const i32 b1 = ld_coherent(&bnd[j * (nt + 1) + t + 1]);
+                    pl = b1 - b0;
+                    moff = a.yrow[y] + b0;
+                }
+                i32 tot;
+                const i32 incl = block_incl_scan_i32<BLOCK>(pl, s_wave, tot);
+                if (tot == 0) continue;  // block-uniform
+                any = true;
+                s_pre[threadIdx.x] = incl;
+                s_moff[threadIdx.x] = moff;
+                __syncthreads();
+                for (i32 k = threadIdx.x; k < tot; k += BLOCK) {
+                    int lo = 0, hi = BLOCK - 1;
+                    while (lo < hi) {
+                        int md = (lo + hi) >> 1;
+                        if (s_pre[md] > k) hi = md; else lo = md + 1;
+                    }
+                    const i32 before = lo ? s_pre[lo - 1] : 0;
+                    const i32 xp = a.yadj[s_moff[lo] + (k - before)];
+                    if (xp == x) continue;
+                    ++tl.wedges;
+                    const i32 o = xp - r0;
+                    atomicAdd(&cnt[o >> 1], 1u << ((o & 1) << 4));
+                }
+                __syncthreads();
+            }
+            if (!any) continue;
+            for (i32 wi = threadIdx.x; wi < WORDS; wi += BLOCK) {
+                const u32 v = cnt[wi];
+                if (!v) continue;
+                cnt[wi] = 0;
+                for (int h = 0; h < 2; ++h) {
+                    const u64 cc = (v >> (16 * h)) & 0xFFFFu;
+                    if (cc < 2) continue;
+                    const i32 xp = r0 + 2 * wi + h;
+                    if (a.st[xp] != ST_ALIVE) continue;
+                    const u64 dd = cc * (cc - 1) / 2;
+                    const u64 old = atomicAdd((unsigned long long *)&a.sup[xp], (unsigned long long)(0ull - dd));
+                    ++tl.atomics;
+                    if (old >= B && old - dd < B) {
+                        u32 p = atomicAdd(a.nnf, 1u);
+                        a.nf[p] = xp;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    tl.flush(a.kc, a.wedges);
+}
+
+// Heavy active vertices, streaming form: every wedge issues one
+// fire-and-forget increment of a per-workgroup HBM counter c[x'] and sets
+// bit x' of a touched bitmap held in LDS (one bit per X vertex).  After the
+// vertex's wedges, the bitmap is scanned; each touched counter is read,
+// cleared, and turned into the C(c, 2) update.  Waves never wait on an
+// atomic's return value while streaming wedges.
+template <int NBW>
+__global__ __launch_bounds__(512) void k_tip_peel_bits(PeelArgs a, int bin) {
+    constexpr int BLOCK = 512;
+    __shared__ u32 bm[NBW];
+    __shared__ i32 s_pre[BLOCK];
+    __shared__ i64 s_moff[BLOCK];
+    __shared__ i32 s_wave[BLOCK / WAVE];
+    __shared__ i32 s_item;
+    const i32 nwords = (i32)((a.nx + 31) >> 5);
+    for (i32 i = threadIdx.x; i < nwords; i += BLOCK) bm[i] = 0;
+    u32 *cnt = a.dcnt + (i64)blockIdx.x * a.nx;
+    const u32 n = a.nitems[bin];
+    const u64 B = *a.bound;
+    Tally tl;
+    __syncthreads();
+    for (;;) {
+        if (threadIdx.x == 0) s_item = (i32)atomicAdd(&a.next[bin], 1u);
+        __syncthreads();
+        const i32 item = s_item;
+        __syncthreads();
+        if ((u32)item >= n) break;
+        const i32 x = a.items[item];
+        const i64 jb = a.xrow[x], je = a.xrow[x + 1];
+        if (threadIdx.x == 0) {
+            tl.segments += (u64)(je - jb);
+            tl.items += 1;
+        }
+        for (i64 cb = jb; cb < je; cb += BLOCK) {
+            const i64 j = cb + threadIdx.x;
+            i32 pl = 0;
+            i64 moff = 0;
+            if (j < je) {
+                const i32 y = a.xadj[j];
+                pl = a.ylen[y];
+                moff = a.yrow[y];
+            }
+            i32 tot;
+            const i32 incl = block_incl_scan_i32<BLOCK>(pl, s_wave, tot);
+            if (tot == 0) continue;  // block-uniform
+            s_pre[threadIdx.x] = incl;
+            s_moff[threadIdx.x] = moff;
+            __syncthreads();
+            for (i32 k = threadIdx.x; k < tot; k += BLOCK) {
+                int lo = 0, hi = BLOCK - 1;
+                while (lo < hi) {
+                    int md = (lo + hi) >> 1;
+                    if (s_pre[md] > k) hi = md; else lo = md + 1;
+                }
+                const i32 before = lo ? s_pre[lo - 1] : 0;
+                const i32 xp = a.yadj[s_moff[lo] + (k - before)];
+                if (xp == x) continue;
+                ++tl.wedges;
+                // the counters are private to this workgroup: workgroup scope
+                // keeps the increment in this XCD's L2
+                __hip_atomic_fetch_add(&cnt[xp], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                atomicOr(&bm[xp >> 5], 1u << (xp & 31));
+            }
+            __syncthreads();
+        }
+        // every wave waits for its increments to complete before the scan
+        __threadfence();
+        __syncthreads();
+        for (i32 wi = threadIdx.x; wi < nwords; wi += BLOCK) {
+            u32 v = bm[wi];
+            if (!v) continue;
+            bm[wi] = 0;
+            while (v) {
+                const int b = __ffs(v) - 1;
+                v &= v - 1;
+                const i32 xp = (wi << 5) + b;
+                const u64 cc = __hip_atomic_exchange(&cnt[xp], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (cc < 2 || a.st[xp] != ST_ALIVE) continue;
+                const u64 dd = cc * (cc - 1) / 2;
+                const u64 old = atomicAdd((unsigned long long *)&a.sup[xp], (unsigned long long)(0ull - dd));
+                ++tl.atomics;
+                if (old >= B && old - dd < B) {
+                    u32 p = atomicAdd(a.nnf, 1u);
+                    a.nf[p] = xp;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    tl.flush(a.kc, a.wedges);
+}
+
+// ------------------------------------------------------------------ pull rounds
+// For large active sets the same updates are computed from the receiving
+// side.  Every Y vertex touched by the active set gets the list of its
+// active neighbours (by index f into the active set); each alive x' next to
+// a touched y then counts c(x', f) over y in N_x' in LDS and lowers its own
+// support by the sum of C(c, 2): one owner per x', no atomics per wedge, and
+// the active lists are small enough to stay in cache.
+
+struct PullArgs {
+    const i64 *xrow;
+    const i32 *xadj;
+    const i32 *F;        // active set
+    const u32 *nF;
+    const i32 *acnt;     // [ny] active neighbours of y (0 if untouched)
+    const i64 *aoff;     // [ny] start of y's active list in act
+    const i32 *act;      // active lists (indices into F)
+    const u64 *wp;       // [nx] pull wedges of x'
+    const i32 *items;
+    const u32 *nitems;
+    u32 *next;
+    u64 *sup;
+    const u64 *bound;
+    i32 *nf;
+    u32 *nnf;
+    u32 *dcnt;           // HBM counters over active indices, per workgroup
+    i32 *dtouch;
+    u32 *dntouch;
+    i64 dstride;
+    u64 *wedges;
+    KCounters *kc;
+};
+
+// y's touched by the active set: count active neighbours, list the y's
+__global__ void k_act_count(const i32 *F, const u32 *nF, const i64 *xrow, const i32 *xadj, i32 *acnt, i32 *ytouch,
+                            u32 *nytouch) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const i64 wave = (blockIdx.x * (i64)blockDim.x + threadIdx.x) / WAVE;
+    const i64 nwaves = (i64)gridDim.x * blockDim.x / WAVE;
+    const u32 n = *nF;
+    for (i64 f = wave; f < n; f += nwaves) {
+        const i32 x = F[f];
+        for (i64 j = xrow[x] + lane; j < xrow[x + 1]; j += WAVE) {
+            const i32 y = xadj[j];
+            if (atomicAdd(&acnt[y], 1) == 0) {
+                u32 p = atomicAdd(nytouch, 1u);
+                ytouch[p] = y;
+            }
+        }
+    }
+}
+
+__global__ void k_act_gather(const i32 *ytouch, const u32 *nytouch, const i32 *acnt, i64 *tmp) {
+    const u32 n = *nytouch;
+    for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x)
+        tmp[i] = acnt[ytouch[i]];
+}
+
+__global__ void k_act_offsets(const i32 *ytouch, const u32 *nytouch, const i64 *pre, i64 *aoff, i32 *acur) {
+    const u32 n = *nytouch;
+    for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) {
+        const i32 y = ytouch[i];
+        aoff[y] = pre[i];
+        acur[y] = 0;
+    }
+}
+
+__global__ void k_act_fill(const i32 *F, const u32 *nF, const i64 *xrow, const i32 *xadj, const i64 *aoff, i32 *acur,
+                           i32 *act) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const i64 wave = (blockIdx.x * (i64)blockDim.x + threadIdx.x) / WAVE;
+    const i64 nwaves = (i64)gridDim.x * blockDim.x / WAVE;
+    const u32 n = *nF;
+    for (i64 f = wave; f < n; f += nwaves) {
+        const i32 x = F[f];
+        for (i64 j = xrow[x] + lane; j < xrow[x + 1]; j += WAVE) {
+            const i32 y = xadj[j];
+            act[aoff[y] + atomicAdd(&acur[y], 1)] = (i32)f;
+        }
+    }
+}
+
+// Receivers: alive x' in the live list of a touched y; wp[x'] accumulates
+// sum over y of |active neighbours of y| (the pull wedges of x').  One wave
+// per touched y.
+__global__ void k_pull_discover(const i32 *ytouch, const u32 *nytouch, const i64 *yrow, const i32 *yadj, const i32 *ylen,
+                                const i32 *acnt, const unsigned char *st, u64 *wp, i32 *rlist, u32 *nr) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const i64 wave = (blockIdx.x * (i64)blockDim.x + threadIdx.x) / WAVE;
+    const i64 nwaves = (i64)gridDim.x * blockDim.x / WAVE;
+    const u32 n = *nytouch;
+    for (i64 i = wave; i < n; i += nwaves) {
+        const i32 y = ytouch[i];
+        const u32 a = (u32)acnt[y];
+        const i64 b = yrow[y];
+        const i32 len = ylen[y];
+        for (i32 k = lane; k < len; k += WAVE) {
+            const i32 xp = yadj[b + k];
+            if (st[xp] != ST_ALIVE) continue;
+            if (atomicAdd((unsigned long long *)&wp[xp], (unsigned long long)a) == 0) {
+                u32 p = atomicAdd(nr, 1u);
+                rlist[p] = xp;
+            }
+        }
+    }
+}
+
+// bins of receivers: small / medium LDS hash, large (LDS dense or HBM)
+__global__ void k_pull_bin(const i32 *rlist, const u32 *nr, const u64 *wp, i32 *lists, i64 stride, u32 *nbin, u64 *wsum) {
+    const u32 n = *nr;
+    u64 s = 0;
+    for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) {
+        const i32 xp = rlist[i];
+        const u64 w = wp[xp];
+        s += w;
+        if (w < 2) continue;
+        const int b = w <= (u64)T_SMALL_W ? 0 : (w <= (u64)T_MEDIUM_W ? 1 : 2);
+        const u32 p = atomicAdd(&nbin[b], 1u);
+        lists[b * stride + p] = xp;
+    }
+    for (int d = WAVE / 2; d > 0; d >>= 1) s += __shfl_down(s, d, WAVE);
+    if ((threadIdx.x & 63) == 0 && s) atomicAdd((unsigned long long *)wsum, (unsigned long long)s);
+}
+
+__global__ void k_pull_clear(const i32 *ytouch, const u32 *nytouch, i32 *acnt, const i32 *rlist, const u32 *nr, u64 *wp) {
+    const u32 ny = *nytouch, n = *nr;
+    for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < ny; i += (i64)gridDim.x * blockDim.x) acnt[ytouch[i]] = 0;
+    for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) wp[rlist[i]] = 0;
+}
+
+// One receiver x': count c(x', f) over the active lists of its neighbours,
+// then its support loses the sum of C(c, 2).
+template <int BLOCK, class Acc>
+__device__ __forceinline__ void pull_item(const PullArgs &a, i32 xp, Acc &A, const ItemSmem &sm, Tally &t) {
+    const i64 jb = a.xrow[xp], je = a.xrow[xp + 1];
+    if (threadIdx.x == 0) {
+        t.segments += (u64)(je - jb);
+        t.items += 1;
+    }
+    for (i64 cb = jb; cb < je; cb += BLOCK) {
+        const i64 j = cb + threadIdx.x;
+        i32 pl = 0;
+        i64 moff = 0;
+        if (j < je) {
+            const i32 y = a.xadj[j];
+            pl = a.acnt[y];
+            if (pl) moff = a.aoff[y];
+        }
+        i32 tot;
+        const i32 incl = block_incl_scan_i32<BLOCK>(pl, sm.wave, tot);
+        if (tot == 0) continue;  // block-uniform
+        sm.pre[threadIdx.x] = incl;
+        sm.moff[threadIdx.x] = moff;
+        __syncthreads();
+        for (i32 k = threadIdx.x; k < tot; k += BLOCK) {
+            int lo = 0, hi = BLOCK - 1;
+            while (lo < hi) {
+                int md = (lo + hi) >> 1;
+                if (sm.pre[md] > k) hi = md; else lo = md + 1;
+            }
+            const i32 before = lo ? sm.pre[lo - 1] : 0;
+            A.add(a.act[sm.moff[lo] + (k - before)]);
+            ++t.wedges;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) sm.bcast[0] = A.entries();
+    __syncthreads();
+    const i64 ne = sm.bcast[0];
+    __syncthreads();
+    u64 delta = 0;
+    for (i64 i = threadIdx.x; i < ne; i += BLOCK) {
+        i32 key;
+        u32 c32;
+        A.entry(i, key, c32);
+        if (key < 0 || c32 < 2) continue;
+        const u64 cc = c32;
+        delta += cc * (cc - 1) / 2;
+    }
+    delta = block_sum_u64<BLOCK>(delta, sm.red);
+    if (threadIdx.x == 0 && delta) {
+        const u64 B = *a.bound;
+        const u64 old = a.sup[xp];
+        const u64 nv = old - delta;
+        a.sup[xp] = nv;
+        ++t.atomics;
+        if (old >= B && nv < B) {
+            u32 p = atomicAdd(a.nnf, 1u);
+            a.nf[p] = xp;
+        }
+    }
+    __syncthreads();
+}
+
+template <int BLOCK, int LOGCAP>
+__global__ __launch_bounds__(BLOCK) void k_pull_hash(PullArgs a, int bin) {
+    constexpr int CAP = 1 << LOGCAP;
+    __shared__ i32 s_keys[CAP];
+    __shared__ u32 s_vals[CAP];
+    __shared__ i32 s_pre[BLOCK];
+    __shared__ i64 s_moff[BLOCK];
+    __shared__ i32 s_wave[BLOCK / WAVE];
+    __shared__ u64 s_red[BLOCK / WAVE];
+    __shared__ i64 s_bcast[1];
+    __shared__ i32 s_item;
+    ItemSmem sm{s_pre, s_moff, s_wave, s_red, s_bcast};
+    LdsAcc A;
+    A.keys = s_keys;
+    A.vals = s_vals;
+    A.bids = nullptr;
+    const u32 n = a.nitems[bin];
+    Tally tl;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = (i32)atomicAdd(&a.next[bin], 1u);
+        __syncthreads();
+        const i32 item = s_item;
+        __syncthreads();
+        if ((u32)item >= n) break;
+        const i32 xp = a.items[item];
+        const i64 w = a.wp[xp];
+        int logcap = 6;
+        while ((i64(1) << logcap) < 2 * w && logcap < LOGCAP) ++logcap;
+        A.init(logcap, threadIdx.x, BLOCK);
+        __syncthreads();
+        pull_item<BLOCK>(a, xp, A, sm, tl);
+    }
+    tl.flush(a.kc, a.wedges);
+}
+
+// Large receivers: counters over all active indices, in HBM per workgroup.
+__global__ __launch_bounds__(256) void k_pull_dense(PullArgs a, int bin) {
+    constexpr int BLOCK = 256;
+    __shared__ i32 s_pre[BLOCK];
+    __shared__ i64 s_moff[BLOCK];
+    __shared__ i32 s_wave[BLOCK / WAVE];
+    __shared__ u64 s_red[BLOCK / WAVE];
+    __shared__ i64 s_bcast[1];
+    __shared__ i32 s_item;
+    ItemSmem sm{s_pre, s_moff, s_wave, s_red, s_bcast};
+    DenseAcc A;
+    A.c = a.dcnt + (i64)blockIdx.x * a.dstride;
+    A.bids = nullptr;
+    A.touch = a.dtouch + (i64)blockIdx.x * a.dstride;
+    A.ntouch = a.dntouch + blockIdx.x;
+    const u32 n = a.nitems[bin];
+    Tally tl;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = (i32)atomicAdd(&a.next[bin], 1u);
+        __syncthreads();
+        const i32 item = s_item;
+        __syncthreads();
+        if ((u32)item >= n) break;
+        pull_item<BLOCK>(a, a.items[item], A, sm, tl);
+        A.reset(threadIdx.x, BLOCK);
+    }
+    tl.flush(a.kc, a.wedges);
 }
 
 // ------------------------------------------------------------------ CD helpers
 
-__global__ void k_bin_active(const i32 *F, const u32 *nF, const u64 *w, i32 *lists, i64 stride, u32 *nbin) {
+// Wedges of each active vertex over the live lists (one wave per vertex),
+// their total (the batch rule's wedge count of the active set, Section 5.1),
+// and the work bins: small / medium LDS hash, LDS key tiles, HBM counters.
+__global__ void k_item_work(const i32 *F, const u32 *nF, const i64 *xrow, const i32 *xadj, const i32 *ylen, u64 *wi,
+                            u64 *wsum, i32 *lists, i64 stride, u32 *nbin, int heavy_bin) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const i64 wave = (blockIdx.x * (i64)blockDim.x + threadIdx.x) / WAVE;
+    const i64 nwaves = (i64)gridDim.x * blockDim.x / WAVE;
     const u32 n = *nF;
-    for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) {
-        i32 x = F[i];
-        u64 wx = w[x];
-        int b = wx <= (u64)T_SMALL_W ? 0 : (wx <= (u64)T_MEDIUM_W ? 1 : 2);
-        u32 p = atomicAdd(&nbin[b], 1u);
-        lists[b * stride + p] = x;
+    for (i64 i = wave; i < n; i += nwaves) {
+        const i32 x = F[i];
+        const i64 jb = xrow[x], je = xrow[x + 1];
+        u64 s = 0;
+        for (i64 j = jb + lane; j < je; j += WAVE) s += (u64)ylen[xadj[j]];
+        for (int dd = WAVE / 2; dd > 0; dd >>= 1) s += __shfl_down(s, dd, WAVE);
+        if (lane == 0) {
+            wi[x] = s;
+            atomicAdd((unsigned long long *)wsum, (unsigned long long)s);
+            if (s >= 2) {
+                int b;
+                if (s <= (u64)T_SMALL_W) b = 0;
+                else if (s <= (u64)T_MEDIUM_W) b = 1;
+                else b = heavy_bin;
+                u32 p = atomicAdd(&nbin[b], 1u);
+                lists[b * stride + p] = x;
+            }
+        }
     }
 }
 
@@ -247,7 +750,6 @@ __global__ void k_frontier(unsigned char *st, const u64 *sup, const u64 *w, u64 
             part[x] = pid;
             u32 p = atomicAdd(&ctl->nF, 1u);
             F[p] = (i32)x;
-            atomicAdd((unsigned long long *)&ctl->wF, (unsigned long long)w[x]);
         }
     }
 }
@@ -283,17 +785,13 @@ __global__ void k_retire(const i32 *F, const u32 *nF, const i64 *xrow, const i32
     }
 }
 
-__global__ void k_activate(const i32 *F2, const u32 *nF2, unsigned char *st, i32 *part, const u64 *w, i32 pid, TipCtl *ctl) {
+__global__ void k_activate(const i32 *F2, const u32 *nF2, unsigned char *st, i32 *part, i32 pid) {
     const u32 n = *nF2;
-    u64 s = 0;
     for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) {
         i32 x = F2[i];
         st[x] = ST_ACTIVE;
         part[x] = pid;
-        s += w[x];
     }
-    for (int d = WAVE / 2; d > 0; d >>= 1) s += __shfl_down(s, d, WAVE);
-    if ((threadIdx.x & 63) == 0 && s) atomicAdd((unsigned long long *)&ctl->wF2, (unsigned long long)s);
 }
 
 // In-place compaction of dirty Y lists to their alive entries; one wave per
@@ -328,19 +826,25 @@ __global__ void k_compact(const i32 *dirty, const u32 *ndirty, const i64 *yrow, 
 __global__ void k_set_bound(TipCtl *ctl, int last) {
     ctl->bound = last ? ~0ull : ctl->s + 1;
     ctl->nF = 0;
+    ctl->nF2 = 0;
     ctl->wF = 0;
     ctl->est_final = 0;
+    for (int b = 0; b < 4; ++b) ctl->nbin[b] = ctl->next[b] = 0;
+    ctl->nyt = ctl->nrecv = 0;
 }
 
 __global__ void k_next_round(TipCtl *ctl) {
     // next active set becomes current; counters of the round are cleared
     ctl->nF = ctl->nF2;
-    ctl->wF = ctl->wF2;
     ctl->nF2 = 0;
-    ctl->wF2 = 0;
-    ctl->nbin[0] = ctl->nbin[1] = ctl->nbin[2] = 0;
-    ctl->next[0] = ctl->next[1] = ctl->next[2] = 0;
+    ctl->wF = 0;
+    for (int b = 0; b < 4; ++b) ctl->nbin[b] = ctl->next[b] = 0;
     ctl->ndirty = 0;
+    ctl->nyt = ctl->nrecv = 0;
+}
+
+__global__ void k_clear_bins(TipCtl *ctl) {
+    for (int b = 0; b < 4; ++b) ctl->nbin[b] = ctl->next[b] = 0;
 }
 
 __global__ void k_scale(TipCtl *ctl) {
@@ -446,6 +950,7 @@ struct FdArgs {
     i32 *lbatch;
     i64 maxni;
     u64 *wedges;
+    KCounters *kc;
 };
 
 // One workgroup peels one partition at a time with sequential bottom-up
@@ -560,7 +1065,9 @@ __global__ __launch_bounds__(256) void k_tip_fd(FdArgs a) {
             __syncthreads();
         }
     }
-    if (wedges) atomicAdd((unsigned long long *)a.wedges, (unsigned long long)wedges);
+    Tally tl;
+    tl.wedges = wedges;
+    tl.flush(a.kc, a.wedges);
 }
 
 // ---- FD preparation kernels
@@ -705,7 +1212,8 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
     i32 *yadj = c.alloc<i32>(m);
     i32 *F = c.alloc<i32>(nx);
     i32 *F2 = c.alloc<i32>(nx);
-    i32 *bins = c.alloc<i32>(3 * nx);
+    i32 *bins = c.alloc<i32>(4 * nx);
+    u64 *wi = c.alloc<u64>(nx);
     TipCtl *ctl = c.alloc<TipCtl>(1);
     PBNG_HIP(hipMemsetAsync(st, 0, nx, s));
     PBNG_HIP(hipMemsetAsync(ydirty, 0, ny + 4, s));
@@ -737,6 +1245,50 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
     unsigned char *alive_label = c.alloc<unsigned char>(G.n);
     u64 *sup_label = c.alloc<u64>(G.n);
     u64 *rmin = c.alloc<u64>(2);
+    // LDS key tiles for heavy active vertices (one 512-lane workgroup per CU)
+    const i32 ntiles = (i32)((nx + (i64(1) << TILE_LOG) - 1) >> TILE_LOG);
+    const int tslots = c.num_cu;
+    i32 *tbnd = c.alloc<i32>((i64)tslots * TB_LIMIT);
+    // heavy vertices stream into HBM counters with an LDS touched bitmap when
+    // one bit per X vertex fits in LDS
+    constexpr int BITS_NBW = 1 << 15;
+    const int heavy_bin = nx <= (i64)BITS_NBW * 32 ? 2 : 3;
+    // heavy-vertex strategy: LDS key tiles (default) or HBM-counter streaming
+    const char *heavy_env = getenv("PBNG_HEAVY");
+    const bool heavy_tiled = !(heavy_env && heavy_env[0] == 'b');
+    const char *pull_env = getenv("PBNG_PULL_MIN_F");
+    const u32 pull_min_f = pull_env ? (u32)atol(pull_env) : PULL_MIN_F;
+    // pull rounds: active lists of touched Y vertices, receivers
+    i32 *acnt = c.alloc<i32>(ny);
+    i64 *aoff = c.alloc<i64>(ny);
+    i32 *acur = c.alloc<i32>(ny);
+    i32 *ytouch = c.alloc<i32>(ny);
+    i32 *act = c.alloc<i32>(m);
+    u64 *wp = c.alloc<u64>(nx);
+    i32 *rlist = c.alloc<i32>(nx);
+    i64 *atmp = c.alloc<i64>(ny + 1);
+    i64 *apre = c.alloc<i64>(ny + 1);
+    PBNG_HIP(hipMemsetAsync(acnt, 0, sizeof(i32) * (ny ? ny : 1), s));
+    PBNG_HIP(hipMemsetAsync(wp, 0, sizeof(u64) * nx, s));
+    PullArgs qa{};
+    qa.xrow = xrow;
+    qa.xadj = xadj;
+    qa.nF = &ctl->nF;
+    qa.acnt = acnt;
+    qa.aoff = aoff;
+    qa.act = act;
+    qa.wp = wp;
+    qa.nitems = ctl->nbin;
+    qa.next = ctl->next;
+    qa.sup = sup;
+    qa.bound = &ctl->bound;
+    qa.nnf = &ctl->nF2;
+    qa.dcnt = dcnt;
+    qa.dtouch = dtouch;
+    qa.dntouch = dntouch;
+    qa.dstride = nx;
+    qa.wedges = &ctl->wedges;
+    qa.kc = c.kctr + PBNG_K_TIP_PEEL;
 
     PeelArgs pa{};
     pa.xrow = xrow;
@@ -748,14 +1300,18 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
     pa.next = ctl->next;
     pa.st = st;
     pa.sup = sup;
-    pa.w = w;
+    pa.wi = wi;
     pa.bound = &ctl->bound;
     pa.nnf = &ctl->nF2;
     pa.dcnt = dcnt;
     pa.dtouch = dtouch;
     pa.dntouch = dntouch;
+    pa.tbnd = tbnd;
+    pa.tbnd_stride = TB_LIMIT;
+    pa.ntiles = ntiles;
     pa.nx = nx;
     pa.wedges = &ctl->wedges;
+    pa.kc = c.kctr + PBNG_K_TIP_PEEL;
 
     struct HostView {
         u32 nF;
@@ -764,9 +1320,22 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
     i64 n_alive = nx;
     int pid = 0;
     u64 rho = 0, recounts = 0, recount_wedges = 0;
+    const bool trace = getenv("PBNG_TRACE") != nullptr;
+    u64 trace_w = 0;
+    double trace_t = now_ms();
     const int gx = grid_1d(nx);
+    auto item_work = [&](i32 *cur) {
+        hipLaunchKernelGGL(k_item_work, dim3(grid_1d((i64)nx * WAVE)), dim3(256), 0, s, (const i32 *)cur,
+                           (const u32 *)&ctl->nF, xrow, xadj, (const i32 *)ylen, wi, &ctl->wF, bins, nx, ctl->nbin,
+                           heavy_bin);
+        PBNG_LAUNCH_CHECK();
+    };
     while (n_alive > 0) {
         const bool last = (P - pid) <= 1;
+        // work estimate of every alive vertex with the current live degrees
+        hipLaunchKernelGGL(k_work_full, dim3(grid_1d(nx * WAVE)), dim3(256), 0, s, xrow, xadj, (const i32 *)ydeg,
+                           (const unsigned char *)st, nx, w);
+        PBNG_LAUNCH_CHECK();
         if (!last) {
             if (o.bound_rule == PBNG_BOUND_RANDOM) {
                 u64 init2[2] = {~0ull, 0};
@@ -784,6 +1353,7 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
         hipLaunchKernelGGL(k_frontier, dim3(gx), dim3(256), 0, s, st, (const u64 *)sup, (const u64 *)w, init, wsnap, part,
                            nx, ctl, pid, 1, F);
         PBNG_LAUNCH_CHECK();
+        item_work(F);
         HostView hv;
         PBNG_HIP(hipMemcpyAsync(&hv.nF, &ctl->nF, sizeof(u32), hipMemcpyDeviceToHost, s));
         PBNG_HIP(hipMemcpyAsync(&hv.wF, &ctl->wF, sizeof(u64), hipMemcpyDeviceToHost, s));
@@ -811,8 +1381,6 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
                 recount_wedges += count_pass(c, G, sup_label, nullptr, alive_label);
                 hipLaunchKernelGGL(k_from_label, dim3(gx), dim3(256), 0, s, (const u64 *)sup_label, (const i32 *)G.label, xoff,
                                    nx, (const unsigned char *)st, sup);
-                hipLaunchKernelGGL(k_work_full, dim3(grid_1d(nx * WAVE)), dim3(256), 0, s, xrow, xadj, (const i32 *)ydeg,
-                                   (const unsigned char *)st, nx, w);
                 PBNG_LAUNCH_CHECK();
                 ++recounts;
                 n_alive -= nF;
@@ -825,24 +1393,84 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
                 hipLaunchKernelGGL(k_frontier, dim3(gx), dim3(256), 0, s, st, (const u64 *)sup, (const u64 *)w, init, wsnap,
                                    part, nx, ctl, pid, 0, F);
                 PBNG_LAUNCH_CHECK();
+                item_work(F);
+            } else if (nF >= pull_min_f) {
+                // receiving-side round: active lists of the touched Y vertices
+                const int gfw = grid_1d((i64)nF * WAVE);
+                c.kbegin(PBNG_K_TIP_PEEL);
+                hipLaunchKernelGGL(k_act_count, dim3(gfw), dim3(256), 0, s, (const i32 *)F, (const u32 *)&ctl->nF, xrow, xadj,
+                                   acnt, ytouch, &ctl->nyt);
+                PBNG_LAUNCH_CHECK();
+                const u32 nyt = read_scalar<u32>(c, &ctl->nyt);
+                const int gy = grid_1d(std::max<i64>(nyt, 1));
+                hipLaunchKernelGGL(k_act_gather, dim3(gy), dim3(256), 0, s, (const i32 *)ytouch, (const u32 *)&ctl->nyt,
+                                   (const i32 *)acnt, atmp);
+                PBNG_LAUNCH_CHECK();
+                exclusive_scan<i64>(c, atmp, apre, nyt);
+                hipLaunchKernelGGL(k_act_offsets, dim3(gy), dim3(256), 0, s, (const i32 *)ytouch, (const u32 *)&ctl->nyt,
+                                   (const i64 *)apre, aoff, acur);
+                hipLaunchKernelGGL(k_act_fill, dim3(gfw), dim3(256), 0, s, (const i32 *)F, (const u32 *)&ctl->nF, xrow, xadj,
+                                   (const i64 *)aoff, acur, act);
+                hipLaunchKernelGGL(k_pull_discover, dim3(grid_1d((i64)std::max<u32>(nyt, 1) * WAVE)), dim3(256), 0, s,
+                                   (const i32 *)ytouch, (const u32 *)&ctl->nyt, yrow, (const i32 *)yadj, (const i32 *)ylen,
+                                   (const i32 *)acnt, (const unsigned char *)st, wp, rlist, &ctl->nrecv);
+                hipLaunchKernelGGL(k_clear_bins, dim3(1), dim3(1), 0, s, ctl);
+                hipLaunchKernelGGL(k_pull_bin, dim3(grid_1d(nx)), dim3(256), 0, s, (const i32 *)rlist, (const u32 *)&ctl->nrecv,
+                                   (const u64 *)wp, bins, nx, ctl->nbin, &ctl->pw);
+                PBNG_LAUNCH_CHECK();
+                qa.F = F;
+                qa.nf = F2;
+                PullArgs q2 = qa;
+                q2.items = bins + 2 * nx;
+                PullArgs q1 = qa;
+                q1.items = bins + nx;
+                PullArgs q0 = qa;
+                q0.items = bins;
+                hipLaunchKernelGGL(k_pull_dense, dim3(slots), dim3(256), 0, s, q2, 2);
+                hipLaunchKernelGGL((k_pull_hash<256, 13>), dim3((i64)c.num_cu * 2), dim3(256), 0, s, q1, 1);
+                hipLaunchKernelGGL((k_pull_hash<64, 10>), dim3((i64)c.num_cu * 16), dim3(64), 0, s, q0, 0);
+                hipLaunchKernelGGL(k_pull_clear, dim3(grid_1d(nx)), dim3(256), 0, s, (const i32 *)ytouch,
+                                   (const u32 *)&ctl->nyt, acnt, (const i32 *)rlist, (const u32 *)&ctl->nrecv, wp);
+                c.kend(PBNG_K_TIP_PEEL);
+                PBNG_LAUNCH_CHECK();
             } else {
                 pa.items = bins;
                 pa.nf = F2;
-                hipLaunchKernelGGL(k_bin_active, dim3(grid_1d(nF)), dim3(256), 0, s, (const i32 *)F, (const u32 *)&ctl->nF,
-                                   (const u64 *)w, bins, nx, ctl->nbin);
-                PBNG_LAUNCH_CHECK();
                 PeelArgs pd = pa;
-                pd.items = bins + 2 * nx;
-                hipLaunchKernelGGL(k_tip_peel_dense, dim3(std::min<i64>(slots, nF)), dim3(256), 0, s, pd, 2);
+                pd.items = bins + 3 * nx;
+                PeelArgs pt = pa;
+                pt.items = bins + 2 * nx;
                 PeelArgs pm = pa;
                 pm.items = bins + nx;
+                c.kbegin(PBNG_K_TIP_PEEL);
+                hipLaunchKernelGGL(k_tip_peel_dense, dim3(std::min<i64>(slots, nF)), dim3(256), 0, s, pd, 3);
+                if (heavy_bin == 2 && heavy_tiled)
+                    hipLaunchKernelGGL(k_tip_peel_tiled<TILE_LOG>, dim3(std::min<i64>(tslots, nF)), dim3(512), 0, s, pt, 2);
+                else if (heavy_bin == 2)
+                    hipLaunchKernelGGL(k_tip_peel_bits<BITS_NBW>, dim3(std::min<i64>(slots, nF)), dim3(512), 0, s, pt, 2);
                 hipLaunchKernelGGL((k_tip_peel_hash<256, 13>), dim3(std::min<i64>((i64)c.num_cu * 2, nF)), dim3(256), 0, s, pm, 1);
                 hipLaunchKernelGGL((k_tip_peel_hash<64, 10>), dim3(std::min<i64>((i64)c.num_cu * 16, nF)), dim3(64), 0, s, pa, 0);
+                c.kend(PBNG_K_TIP_PEEL);
                 PBNG_LAUNCH_CHECK();
+            }
+            if (!(batch && hv.wF > wedge_cnt_bound)) {
+                if (trace) {
+                    u32 nb[4];
+                    u64 wtot;
+                    PBNG_HIP(hipMemcpyAsync(nb, ctl->nbin, sizeof(nb), hipMemcpyDeviceToHost, s));
+                    PBNG_HIP(hipMemcpyAsync(&wtot, &ctl->wedges, sizeof(u64), hipMemcpyDeviceToHost, s));
+                    PBNG_HIP(hipStreamSynchronize(s));
+                    double tnow = now_ms();
+                    fprintf(stderr, "[pbng-trace] part %d round %llu nF %u wF %llu bins %u/%u/%u/%u wedges %llu ms %.3f\n",
+                            pid, (unsigned long long)rho, nF, (unsigned long long)hv.wF, nb[0], nb[1], nb[2], nb[3],
+                            (unsigned long long)(wtot - trace_w), tnow - trace_t);
+                    trace_w = wtot;
+                    trace_t = tnow;
+                }
                 hipLaunchKernelGGL(k_retire, dim3(gw), dim3(256), 0, s, (const i32 *)F, (const u32 *)&ctl->nF, xrow, xadj, st,
                                    ydeg, ydirty, dirty, &ctl->ndirty, (const u64 *)wsnap, ctl, dynamic ? 1 : 0);
                 hipLaunchKernelGGL(k_activate, dim3(grid_1d(nx)), dim3(256), 0, s, (const i32 *)F2, (const u32 *)&ctl->nF2, st,
-                                   part, (const u64 *)w, pid, ctl);
+                                   part, pid);
                 PBNG_LAUNCH_CHECK();
                 if (dynamic) {
                     hipLaunchKernelGGL(k_compact, dim3(grid_1d((i64)ny * WAVE)), dim3(256), 0, s, (const i32 *)dirty,
@@ -852,6 +1480,7 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
                 n_alive -= nF;
                 hipLaunchKernelGGL(k_next_round, dim3(1), dim3(1), 0, s, ctl);
                 std::swap(F, F2);
+                item_work(F);
             }
             PBNG_HIP(hipMemcpyAsync(&hv.nF, &ctl->nF, sizeof(u32), hipMemcpyDeviceToHost, s));
             PBNG_HIP(hipMemcpyAsync(&hv.wF, &ctl->wF, sizeof(u64), hipMemcpyDeviceToHost, s));
@@ -949,8 +1578,11 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
     fa.ltouch = c.alloc<i32>((i64)fdblocks * maxni);
     fa.lbatch = c.alloc<i32>((i64)fdblocks * maxni);
     fa.wedges = c.alloc<u64>(1);
+    fa.kc = c.kctr + PBNG_K_FD;
     PBNG_HIP(hipMemsetAsync(fa.wedges, 0, sizeof(u64), s));
+    c.kbegin(PBNG_K_FD);
     hipLaunchKernelGGL(k_tip_fd, dim3(fdblocks), dim3(256), 0, s, fa);
+    c.kend(PBNG_K_FD);
     PBNG_LAUNCH_CHECK();
     c.stats.wedges_fd = read_scalar<u64>(c, fa.wedges);
     c.stats.ms_fd = now_ms() - t3;
