@@ -489,6 +489,7 @@ void build_be_index(Ctx &c, const DevGraph &G, BEIndex &I, u64 *sup_edge) {
     I.bk = c.alloc<u32>(I.nblooms);
     I.bedge = c.alloc<i32>(2 * I.npairs);
     i32 *pbloom = c.alloc<i32>(I.npairs);
+    I.pbloom = pbloom;
     // fill (also the per-edge supports)
     a.bbase = bbase;
     a.pbase = pbase;

@@ -134,6 +134,7 @@ struct BEIndex {
     i64 *eoff = nullptr;   // [m+1] link offsets per edge
     i32 *ebloom = nullptr; // [2*npairs] bloom of each link
     i32 *etwin = nullptr;  // [2*npairs] twin edge of each link
+    i32 *pbloom = nullptr; // [npairs] bloom of each pair
 };
 void build_be_index(Ctx &c, const DevGraph &G, BEIndex &I, u64 *sup_edge);
 

@@ -1,0 +1,86 @@
+"""Parity of wing decomposition on the GPU with the CPU oracle (bit-exact),
+plus invariance under the schedule knobs and the BE-Index invariants."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2110_12511_amd as pb
+import synth
+from gpu_util import u64, golden, check_golden
+
+pytestmark = pytest.mark.gpu
+
+
+def gpu_wing(ctx, g, **kw):
+    dg = pb.DeviceGraph.from_graph(g)
+    return u64(pb.wing(ctx, dg, pb.make_opts(**kw) if kw else None))
+
+
+def test_wing_tiny_random(ctx):
+    for s in range(60):
+        rng = np.random.default_rng(300 + s)
+        g = synth.random_small(int(rng.integers(1, 10)), int(rng.integers(1, 10)), float(rng.choice([0.3, 0.6, 0.9])), seed=s)
+        exp = oracle.wing(g)
+        for P in (1, 2, 5):
+            assert np.array_equal(gpu_wing(ctx, g, P=P), exp), (g.name, P)
+
+
+@pytest.mark.parametrize("a,b", [(2, 2), (3, 5), (9, 7), (30, 25)])
+def test_wing_complete(ctx, a, b):
+    g = synth.complete(a, b)
+    for P in (1, 3):
+        assert (gpu_wing(ctx, g, P=P) == (a - 1) * (b - 1)).all()
+
+
+def test_wing_k22_pendant_and_empty(ctx):
+    # one peeled edge of K_{2,2} must leave its twin with support 0, not a
+    # wrapped negative value (twin loses k_B - 1 = 1)
+    g = synth.from_edges(3, 3, [(0, 0), (0, 1), (1, 0), (1, 1), (2, 2)])
+    assert gpu_wing(ctx, g, P=2).tolist() == [1, 1, 1, 1, 0]
+    g2 = synth.from_edges(3, 3, [(0, 0), (2, 2)])
+    assert gpu_wing(ctx, g2).tolist() == [0, 0]
+
+
+def test_wing_er_small_config(ctx):
+    g = synth.config_graph("er_2k_1k_20k")
+    res = gpu_wing(ctx, g, P=8)
+    check_golden(golden("er_2k_1k_20k", "wing"), res, g.digest())
+
+
+@pytest.fixture(scope="module")
+def cl_wing():
+    g = synth.chung_lu(20000, 5000, 150000, 2.1, 1500, seed=5)
+    return g, oracle.wing(g)
+
+
+@pytest.mark.parametrize("P", [0, 1, 9, 400, 3000])
+def test_wing_power_law_partitions(ctx, cl_wing, P):
+    g, exp = cl_wing
+    assert np.array_equal(gpu_wing(ctx, g, P=P), exp)
+
+
+def test_wing_no_dynamic_and_random_bounds(ctx, cl_wing):
+    g, exp = cl_wing
+    assert np.array_equal(gpu_wing(ctx, g, P=50, flags=pb.F_NO_DYNAMIC), exp)
+    for seed in (1, 2):
+        assert np.array_equal(gpu_wing(ctx, g, P=80, bound_rule=pb.BOUND_RANDOM, seed=seed), exp)
+
+
+def test_wing_stats_be_index(ctx, cl_wing):
+    g, exp = cl_wing
+    gpu_wing(ctx, g, P=400)
+    st = ctx.stats()
+    # Property 2: every butterfly lies in exactly one bloom, so the pairs of
+    # pairs over all blooms count the butterflies; here only sizes are checked
+    assert st["blooms"] > 0 and st["bloom_pairs"] >= 2 * st["blooms"]
+    assert st["partitions"] >= 1 and st["rho"] >= 1
+
+
+def test_wing_full_size_golden(ctx):
+    wl = "cl_500k_100k_5m"
+    rec = golden(wl, "wing")
+    if rec is None:
+        pytest.skip("no stored oracle result")
+    g = synth.config_graph(wl)
+    res = gpu_wing(ctx, g, P=400)
+    check_golden(rec, res, g.digest())
