@@ -156,46 +156,48 @@ int orc_count_edge(i64 n_u, i64 n_v, const i64 *row_ptr, const i32 *col, u64 *ou
 }
 
 /* ---------------------------------------------------------------------- */
-/* Binary min-heap of (key, id) with lazy deletion.                         */
+/* Indexed binary min-heap over vertex ids ordered by (key[id], id): each    */
+/* vertex sits in the heap once; a lowered key moves it up (keys only       */
+/* decrease while peeling), so memory stays O(n).                           */
 /* ---------------------------------------------------------------------- */
 
-typedef struct { u64 key; i64 id; } hitem;
-typedef struct { hitem *a; i64 n, cap; } heap;
+typedef struct { i64 *a; i64 *pos; const u64 *key; i64 n; } iheap;
 
-static int hpush(heap *h, u64 key, i64 id)
+static int ih_less(const iheap *h, i64 x, i64 y)
 {
-    if (h->n == h->cap) {
-        i64 nc = h->cap ? 2 * h->cap : 1024;
-        hitem *na = realloc(h->a, (size_t)nc * sizeof(hitem));
-        if (!na) return -3;
-        h->a = na; h->cap = nc;
-    }
-    i64 i = h->n++;
-    while (i > 0) {
-        i64 p = (i - 1) / 2;
-        if (h->a[p].key < key || (h->a[p].key == key && h->a[p].id <= id)) break;
-        h->a[i] = h->a[p];
-        i = p;
-    }
-    h->a[i].key = key; h->a[i].id = id;
-    return 0;
+    return h->key[x] < h->key[y] || (h->key[x] == h->key[y] && x < y);
 }
 
-static hitem hpop(heap *h)
+static void ih_place(iheap *h, i64 i, i64 x) { h->a[i] = x; h->pos[x] = i; }
+
+static void ih_up(iheap *h, i64 i)
 {
-    hitem top = h->a[0];
-    hitem last = h->a[--h->n];
+    i64 x = h->a[i];
+    while (i > 0) {
+        i64 p = (i - 1) / 2;
+        if (!ih_less(h, x, h->a[p])) break;
+        ih_place(h, i, h->a[p]);
+        i = p;
+    }
+    ih_place(h, i, x);
+}
+
+static i64 ih_pop(iheap *h)
+{
+    i64 top = h->a[0];
+    h->pos[top] = -1;
+    i64 x = h->a[--h->n];
+    if (h->n == 0) return top;
     i64 i = 0;
     for (;;) {
-        i64 l = 2 * i + 1, r = l + 1, s = i;
-        hitem best = last;
-        if (l < h->n && (h->a[l].key < best.key || (h->a[l].key == best.key && h->a[l].id < best.id))) { best = h->a[l]; s = l; }
-        if (r < h->n && (h->a[r].key < best.key || (h->a[r].key == best.key && h->a[r].id < best.id))) { best = h->a[r]; s = r; }
-        if (s == i) break;
-        h->a[i] = h->a[s];
+        i64 l = 2 * i + 1, r = l + 1, s = -1;
+        if (l < h->n && ih_less(h, h->a[l], x)) s = l;
+        if (r < h->n && ih_less(h, h->a[r], s < 0 ? x : h->a[l])) s = r;
+        if (s < 0) break;
+        ih_place(h, i, h->a[s]);
         i = s;
     }
-    if (h->n > 0) h->a[i] = last;
+    ih_place(h, i, x);
     return top;
 }
 
@@ -221,20 +223,22 @@ static int tip_left(i64 n_l, const i64 *lptr, const i32 *ladj, const i64 *rptr,
     u64 *cnt = calloc((size_t)(n_l ? n_l : 1), sizeof(u64));
     i32 *touched = malloc((size_t)(n_l ? n_l : 1) * sizeof(i32));
     unsigned char *alive = malloc((size_t)(n_l ? n_l : 1));
-    heap h = {0};
+    iheap h = {0};
+    h.a = malloc((size_t)(n_l ? n_l : 1) * sizeof(i64));
+    h.pos = malloc((size_t)(n_l ? n_l : 1) * sizeof(i64));
+    h.key = sup;
     int rc = 0;
-    if (!sup || !cnt || !touched || !alive) { rc = -3; goto out; }
+    if (!sup || !cnt || !touched || !alive || !h.a || !h.pos) { rc = -3; goto out; }
     rc = count_left(n_l, lptr, ladj, rptr, radj, sup, NULL);
     if (rc) goto out;
     for (i64 u = 0; u < n_l; ++u) {
         alive[u] = 1;
-        if ((rc = hpush(&h, sup[u], u))) goto out;
+        ih_place(&h, h.n, u);
+        ih_up(&h, h.n++);
     }
     u64 wedges = 0, peeled = 0;
     while (h.n > 0) {
-        hitem it = hpop(&h);
-        i64 u = it.id;
-        if (!alive[u] || it.key != sup[u]) continue;   /* stale entry */
+        i64 u = ih_pop(&h);
         u64 k = sup[u];
         theta[u] = k;
         alive[u] = 0;
@@ -262,14 +266,14 @@ static int tip_left(i64 n_l, const i64 *lptr, const i32 *ladj, const i64 *rptr,
             if (nv < k) nv = k;
             if (nv != sup[w]) {
                 sup[w] = nv;
-                if ((rc = hpush(&h, nv, w))) goto out;
+                ih_up(&h, h.pos[w]);
             }
         }
         if (wedge_budget && wedges >= wedge_budget) { rc = -9; break; }
     }
     if (stats) { stats[0] = wedges; stats[1] = peeled; }
 out:
-    free(sup); free(cnt); free(touched); free(alive); free(h.a);
+    free(sup); free(cnt); free(touched); free(alive); free(h.a); free(h.pos);
     return rc;
 }
 
