@@ -32,7 +32,12 @@ enum : int {
     M_EDGE = 2,     // per-edge supports (by edge id)
     M_BE_SIZE = 4,  // count blooms / pairs per start
     M_BE_FILL = 8,  // emit blooms and twin pairs (and per-edge supports)
+    M_XSIDE = 16,   // per-vertex supports of one side X only, without the
+                    // butterflies whose two X vertices are both hubs
 };
+
+// Vertex classes for M_XSIDE (by label)
+enum : unsigned char { LC_Y = 0, LC_X = 1, LC_XHUB = 2 };
 
 constexpr u32 NO_BLOOM = 0xFFFFFFFFu;
 
@@ -41,6 +46,7 @@ struct CountArgs {
     const i32 *ladj, *leid, *lpl;
     const i64 *wsum;             // wedges per start (upper bound when filtered)
     const unsigned char *alive;  // by label; null = all alive
+    const unsigned char *lclass; // M_XSIDE: LC_* by label
     u64 *sup_label;              // M_VERTEX
     u64 *sup_edge;               // M_EDGE / M_BE_FILL
     const i32 *starts;           // work list of this bin
@@ -113,10 +119,82 @@ __device__ __forceinline__ void for_each_wedge(const CountArgs &a, i32 s, const 
     }
 }
 
+// One-side counts without hub-hub butterflies.  A butterfly whose highest-
+// priority vertex is on side X pairs a start and a last on X; when both are
+// hubs the start is a hub (the last has at least its degree), and hub starts
+// are never scheduled.  A butterfly whose highest vertex is on Y pairs two X
+// mids of a (start, last) on Y; counts are kept packed per last as
+// (all mids) + 2^16 (hub mids), and a mid's share excludes the other hub
+// mids when it is a hub itself.  Every count is below 2^16 (the host checks
+// the maximum degree).
+template <int BLOCK, class Acc>
+__device__ __forceinline__ void process_start_xside(const CountArgs &a, i32 s, Acc &A, const ChunkSmem &sm, Tally &t) {
+    const unsigned char sc = a.lclass[s];
+    for_each_wedge<BLOCK>(a, s, sm,
+        [&](int, i64 jmid, i32 last, i64) {
+            const u32 inc = (sc == LC_Y && a.lclass[a.ladj[jmid]] == LC_XHUB) ? 0x10001u : 1u;
+            A.add(last, inc);
+            ++t.wedges;
+        },
+        [&](i64) {});
+    if (threadIdx.x == 0) {
+        t.segments += (u64)(a.loff[s + 1] - a.loff[s]);
+        t.items += 1;
+    }
+    if (threadIdx.x == 0) sm.bcast[0] = A.entries();
+    __syncthreads();
+    const i64 ne = sm.bcast[0];
+    __syncthreads();
+    if (sc != LC_Y) {
+        u64 my_start = 0;
+        for (i64 i = threadIdx.x; i < ne; i += BLOCK) {
+            i32 key;
+            u32 v;
+            A.entry(i, key, v);
+            const u64 cc = v & 0xFFFFu;
+            if (key < 0 || cc < 2) continue;
+            const u64 b = cc * (cc - 1) / 2;
+            my_start += b;
+            atomicAdd((unsigned long long *)&a.sup_label[key], (unsigned long long)b);
+            ++t.atomics;
+        }
+        const u64 tt = block_sum_u64<BLOCK>(my_start, sm.red);
+        if (threadIdx.x == 0 && tt) {
+            atomicAdd((unsigned long long *)&a.sup_label[s], (unsigned long long)tt);
+            ++t.atomics;
+        }
+        __syncthreads();
+        return;
+    }
+    sm.agg[threadIdx.x] = 0;
+    __syncthreads();
+    for_each_wedge<BLOCK>(a, s, sm,
+        [&](int seg, i64 jmid, i32 last, i64) {
+            const u32 v = A.cnt(A.find(last));
+            const u64 cc = v & 0xFFFFu;
+            if (cc < 2) return;
+            const u64 hub = v >> 16;
+            const u64 share = a.lclass[a.ladj[jmid]] == LC_XHUB ? cc - hub : cc - 1;
+            if (share) atomicAdd((unsigned long long *)&sm.agg[seg], (unsigned long long)share);
+        },
+        [&](i64 cb) {
+            const u64 g = sm.agg[threadIdx.x];
+            if (g) {
+                atomicAdd((unsigned long long *)&a.sup_label[a.ladj[cb + threadIdx.x]], (unsigned long long)g);
+                ++t.atomics;
+                sm.agg[threadIdx.x] = 0;
+            }
+        });
+}
+
 // Everything done for one start: pass 1 (wedge counts), the per-bloom
 // epilogue, pass 2 (mid and edge contributions, twin pairs).
 template <int BLOCK, int MODE, class Acc>
 __device__ __forceinline__ void process_start(const CountArgs &a, i32 s, Acc &A, const ChunkSmem &sm, Tally &t) {
+    if constexpr ((MODE & M_XSIDE) != 0) {
+        process_start_xside<BLOCK>(a, s, A, sm, t);
+        return;
+    }
     for_each_wedge<BLOCK>(a, s, sm, [&](int, i64, i32 last, i64) { A.add(last); ++t.wedges; }, [&](i64) {});
     if (threadIdx.x == 0) {
         t.segments += (u64)(a.loff[s + 1] - a.loff[s]);
@@ -313,15 +391,22 @@ __global__ __launch_bounds__(256) void k_count_dense(CountArgs a) {
 
 constexpr i64 SMALL_W = 512, MEDIUM_W = 4096;
 
-__global__ void k_bin_starts(const i64 *wsum, const i32 *gid, const unsigned char *alive, i64 n, i32 *lists, u32 *counts) {
-    // lists: [3][n]; counts: [3]
-    for (i64 s = blockIdx.x * (i64)blockDim.x + threadIdx.x; s < n; s += (i64)gridDim.x * blockDim.x) {
-        i64 w = wsum[s];
-        if (w == 0) continue;
-        if (alive && !alive[s]) continue;
-        int b = w <= SMALL_W ? 0 : (w <= MEDIUM_W ? 1 : 2);
-        u32 p = atomicAdd(&counts[b], 1u);
-        lists[(i64)b * n + p] = (i32)s;
+__global__ void k_bin_starts(const i64 *wsum, const unsigned char *lclass, const unsigned char *alive, i64 n, i32 *lists,
+                             u32 *counts) {
+    // lists: [3][n]; counts: [3]; one atomic per wave and bin
+    const i64 stride = (i64)gridDim.x * blockDim.x;
+    const i64 nn = (n + WAVE - 1) / WAVE * WAVE;
+    for (i64 s = blockIdx.x * (i64)blockDim.x + threadIdx.x; s < nn; s += stride) {
+        int b = -1;
+        if (s < n) {
+            const i64 w = wsum[s];
+            const bool skip = w == 0 || (alive && !alive[s]) || (lclass && lclass[s] == LC_XHUB);
+            if (!skip) b = w <= SMALL_W ? 0 : (w <= MEDIUM_W ? 1 : 2);
+        }
+        for (int k = 0; k < 3; ++k) {
+            const u32 p = wave_append(&counts[k], b == k);
+            if (b == k) lists[(i64)k * n + p] = (i32)s;
+        }
     }
 }
 
@@ -335,14 +420,14 @@ struct Bins {
     u32 cnt[3];
 };
 
-static Bins bin_starts(Ctx &c, const DevGraph &G, const unsigned char *alive) {
+static Bins bin_starts(Ctx &c, const DevGraph &G, const unsigned char *alive, const unsigned char *lclass = nullptr) {
     Bins b;
     b.lists = c.alloc<i32>(3 * G.n);
     u32 *counts = c.alloc<u32>(4);
     PBNG_HIP(hipMemsetAsync(counts, 0, 4 * sizeof(u32), c.stream));
     if (G.n) {
-        hipLaunchKernelGGL(k_bin_starts, dim3(gridN(G.n)), dim3(256), 0, c.stream, (const i64 *)G.wsum, (const i32 *)G.gid,
-                           alive, G.n, b.lists, counts);
+        hipLaunchKernelGGL(k_bin_starts, dim3(gridN(G.n)), dim3(256), 0, c.stream, (const i64 *)G.wsum, lclass, alive, G.n,
+                           b.lists, counts);
         PBNG_LAUNCH_CHECK();
     }
     PBNG_HIP(hipMemcpyAsync(b.cnt, counts, 3 * sizeof(u32), hipMemcpyDeviceToHost, c.stream));
@@ -416,6 +501,18 @@ u64 count_pass(Ctx &c, const DevGraph &G, u64 *sup_label, u64 *sup_edge, const u
     if (sup_label && sup_edge) launch_all<M_VERTEX | M_EDGE>(c, G, a, b);
     else if (sup_label) launch_all<M_VERTEX>(c, G, a, b);
     else if (sup_edge) launch_all<M_EDGE>(c, G, a, b);
+    return read_scalar<u64>(c, a.wedges);
+}
+
+u64 count_pass_xside(Ctx &c, const DevGraph &G, u64 *sup_label, const unsigned char *lclass) {
+    CountArgs a = base_args(G);
+    a.lclass = lclass;
+    a.sup_label = sup_label;
+    a.wedges = c.alloc<u64>(1);
+    PBNG_HIP(hipMemsetAsync(a.wedges, 0, sizeof(u64), c.stream));
+    PBNG_HIP(hipMemsetAsync(sup_label, 0, sizeof(u64) * (G.n ? G.n : 1), c.stream));
+    Bins b = bin_starts(c, G, nullptr, lclass);
+    launch_all<M_XSIDE>(c, G, a, b);
     return read_scalar<u64>(c, a.wedges);
 }
 

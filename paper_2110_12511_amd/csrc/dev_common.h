@@ -27,6 +27,21 @@ __device__ __forceinline__ void st_coherent(T *p, T v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Wave-aggregated append: one atomic per wave; returns this lane's slot
+// (meaningful only where pred holds).  Call from every lane of the wave
+// that reaches it.
+__device__ __forceinline__ u32 wave_append(u32 *ctr, bool pred) {
+    const u64 m = __ballot(pred);
+    if (!m) return 0;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    u32 base = 0;
+    if (lane == leader) base = atomicAdd(ctr, (u32)__popcll(m));
+    base = __shfl(base, leader, WAVE);
+    const u64 below = lane ? (~0ull >> (WAVE - lane)) : 0ull;
+    return base + (u32)__popcll(m & below);
+}
+
 // Per-thread tallies of algorithmic work, flushed once per workgroup.
 struct Tally {
     u64 wedges = 0, segments = 0, atomics = 0, items = 0;
@@ -117,7 +132,7 @@ struct LdsAcc {
             vals[i] = 0;
         }
     }
-    __device__ __forceinline__ void add(i32 key) {
+    __device__ __forceinline__ void add(i32 key, u32 inc = 1u) {
         u32 h = hash32((u32)key) >> shift;
         for (;;) {
             i32 k = keys[h];
@@ -128,7 +143,7 @@ struct LdsAcc {
             }
             h = (h + 1) & mask;
         }
-        atomicAdd(&vals[h], 1u);
+        atomicAdd(&vals[h], inc);
     }
     __device__ __forceinline__ i64 entries() const { return (i64)mask + 1; }
     __device__ __forceinline__ void entry(i64 i, i32 &key, u32 &c) const {
@@ -157,8 +172,8 @@ struct DenseAcc {
     i32 *bids;
     i32 *touch;
     u32 *ntouch;
-    __device__ __forceinline__ void add(i32 key) {
-        u32 old = atomicAdd(&c[key], 1u);
+    __device__ __forceinline__ void add(i32 key, u32 inc = 1u) {
+        u32 old = atomicAdd(&c[key], inc);
         if (old == 0) {
             u32 t = atomicAdd(ntouch, 1u);
             __hip_atomic_store(&touch[t], key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

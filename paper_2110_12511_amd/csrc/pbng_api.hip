@@ -169,10 +169,9 @@ int pbng_count(pbng_ctx *x, const pbng_csr *g, pbng_count_kind kind, const pbng_
             co.sup_edge = ob.dev;
             count_butterflies(c, G, co, o);
         } else {
-            CountOut co;
-            co.sup_label = c.alloc<u64>(G.n);
-            count_butterflies(c, G, co, o);
-            gather_side(c, G, co.sup_label, kind == PBNG_COUNT_VERTEX_U ? 0 : 1, ob.dev);
+            const u64 w = count_side(c, G, kind == PBNG_COUNT_VERTEX_U ? 0 : 1, o, ob.dev);
+            c.stats.wedges_count += w;
+            c.stats.wedges += w;
         }
         ob.finish();
         c.stats.ms_count = ms_since(t1);

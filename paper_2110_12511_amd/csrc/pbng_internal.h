@@ -87,6 +87,7 @@ struct Ctx {
 // decreasing degree (ties by increasing global id).
 struct DevGraph {
     i64 n_u = 0, n_v = 0, n = 0, m = 0;
+    i64 maxdeg = 0;
     const i64 *urow = nullptr;  // U-side CSR (caller's, on device)
     const i32 *ucol = nullptr;
     i64 *vrow = nullptr;        // V-side CSR: U ids, and edge ids
@@ -154,6 +155,16 @@ void weighted_select(Ctx &c, const u64 *key, const u64 *w, const unsigned char *
 // Counting pass with an optional alive filter by label (recounts).
 // Returns the wedges walked.  sup_label / sup_edge are overwritten.
 u64 count_pass(Ctx &c, const DevGraph &G, u64 *sup_label, u64 *sup_edge, const unsigned char *alive_label);
+
+// One-side counting without hub-hub butterflies (lclass by label: 0 other
+// side, 1 this side, 2 hub of this side); see count.hip.
+u64 count_pass_xside(Ctx &c, const DevGraph &G, u64 *sup_label, const unsigned char *lclass);
+
+// Per-vertex butterfly counts of one side (0 = U, 1 = V) into out[n_side]:
+// hub-hub butterflies of that side from an int8 Gram matrix on matrix cores
+// when the options allow it (mfma.hip), everything else by traversal.
+// Returns the wedges walked.
+u64 count_side(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 *out);
 
 int bits_for(u64 maxval);
 int grid_1d(i64 n, int block = 256, int cap = 16384);

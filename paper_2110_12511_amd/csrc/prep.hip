@@ -186,6 +186,7 @@ void build_graph(Ctx &c, const pbng_csr &g, DevGraph &G) {
         PBNG_LAUNCH_CHECK();
     }
     i32 maxdeg = read_scalar<i32>(c, dmax);
+    G.maxdeg = maxdeg;
     u64 *dkeys = c.alloc<u64>(n);
     i32 *ids = c.alloc<i32>(n);
     if (n) {

@@ -104,6 +104,9 @@ void Ctx::timing_end_call() {
         s.wedges = h[k].wedges;
         if (k == PBNG_K_WING_CD)
             s.bytes = 8 * h[k].wedges + 16 * h[k].atomics + 16 * h[k].segments + 16 * h[k].items;
+        else if (k == PBNG_K_DENSE)
+            s.bytes = h[k].items;  // int8 tile bytes; wedges holds the int8 ops
+
         else
             s.bytes = 4 * h[k].wedges + 12 * h[k].segments + 16 * h[k].atomics + 16 * h[k].items;
     }

@@ -1189,12 +1189,7 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
 
     // ---- counting
     u64 *sup = c.alloc<u64>(nx);
-    {
-        u64 *sl = c.alloc<u64>(G.n);
-        u64 w = count_pass(c, G, sl, nullptr, nullptr);
-        c.stats.wedges_count += w;
-        gather_side(c, G, sl, side, sup);
-    }
+    c.stats.wedges_count += count_side(c, G, side, o, sup);
     PBNG_HIP(hipStreamSynchronize(s));
     double t1 = now_ms();
     c.stats.ms_count = t1 - t0;

@@ -88,3 +88,41 @@ def test_count_full_size_golden(ctx, quantity):
     kind = pb.COUNT_VERTEX_U if quantity == "count_u" else pb.COUNT_EDGE
     res = u64(pb.count(ctx, dg, kind))
     check_golden(rec, res, g.digest())
+
+
+# ---- hub blocks on matrix cores: identical counts for every cut-over degree
+
+
+def _side_counts(ctx, g, cut):
+    dg = pb.DeviceGraph.from_graph(g)
+    o = pb.make_opts(dense_cut=cut)
+    return (u64(pb.count(ctx, dg, pb.COUNT_VERTEX_U, o)), u64(pb.count(ctx, dg, pb.COUNT_VERTEX_V, o)))
+
+
+@pytest.mark.parametrize("cut", [-1, 1, 2, 5, 40])
+def test_count_dense_tile_cutovers_tiny(ctx, cut):
+    for s in range(25):
+        rng = np.random.default_rng(700 + s)
+        g = synth.random_small(int(rng.integers(2, 40)), int(rng.integers(2, 40)), float(rng.choice([0.2, 0.5, 0.9])), seed=s)
+        ou, ov = oracle.count_vertex(g)
+        bu, bv = _side_counts(ctx, g, cut)
+        assert np.array_equal(bu, ou), (g.name, cut)
+        assert np.array_equal(bv, ov), (g.name, cut)
+
+
+@pytest.mark.parametrize("cut", [-1, 8, 64, 1024])
+def test_count_dense_tile_power_law(ctx, cut):
+    g = synth.chung_lu(30000, 6000, 300000, 2.1, 4000, seed=5)
+    ou, ov = oracle.count_vertex(g)
+    bu, bv = _side_counts(ctx, g, cut)
+    assert np.array_equal(bu, ou) and np.array_equal(bv, ov)
+    st = ctx.stats()
+    if cut > 0:
+        assert st["dense_pairs"] > 0
+
+
+def test_count_dense_tile_complete(ctx):
+    # K_{70,90}: every vertex is a hub at cut 10; all butterflies come from the Gram tile
+    g = synth.complete(70, 90)
+    bu, bv = _side_counts(ctx, g, 10)
+    assert (bu == 69 * (90 * 89 // 2)).all() and (bv == 89 * (70 * 69 // 2)).all()

@@ -109,3 +109,10 @@ def test_tip_full_size_golden(ctx, wl, q):
     g = synth.config_graph(wl)
     res = gpu_tip(ctx, g, 0 if q == "tip_u" else 1, P=150)
     check_golden(rec, res, g.digest())
+
+
+@pytest.mark.parametrize("cut", [-1, 16, 256])
+def test_tip_dense_tile_cutovers(ctx, cl_mid, cut):
+    g, eu, ev = cl_mid
+    assert np.array_equal(gpu_tip(ctx, g, 0, P=150, dense_cut=cut), eu)
+    assert np.array_equal(gpu_tip(ctx, g, 1, P=150, dense_cut=cut), ev)
