@@ -444,6 +444,7 @@ struct WFdArgs {
     i64 tstride;         // ltouch stride: most instances of one partition
     u64 *work;           // links + pair visits
     KCounters *kc;
+    u32 *levels;         // optional: levels peeled per partition
 };
 
 // st: 1 alive, 2 in the current level's batch, 0 peeled
@@ -497,6 +498,7 @@ __global__ __launch_bounds__(256) void k_wing_fd(WFdArgs a) {
             }
             __syncthreads();
             const i32 nb = (i32)s_cnt[0];
+            if (a.levels && threadIdx.x == 0) atomicAdd(&a.levels[pid], 1u);
             // links of the batch: twin updates and dropped-pair counts
             for (i32 cb = 0; cb < nb; cb += BLOCK) {
                 const i32 j = cb + threadIdx.x;
@@ -900,10 +902,27 @@ void wing_decompose(Ctx &c, const DevGraph &G, const pbng_opts &o, u64 *theta) {
     fa.work = c.alloc<u64>(1);
     fa.kc = c.kctr + PBNG_K_FD;
     PBNG_HIP(hipMemsetAsync(fa.work, 0, sizeof(u64), s));
+    const bool trace = getenv("PBNG_TRACE") != nullptr;
+    if (trace) {
+        fa.levels = c.alloc<u32>(np);
+        PBNG_HIP(hipMemsetAsync(fa.levels, 0, sizeof(u32) * np, s));
+    }
     c.kbegin(PBNG_K_FD);
     hipLaunchKernelGGL(k_wing_fd, dim3(fdblocks), dim3(256), 0, s, fa);
     c.kend(PBNG_K_FD);
     PBNG_LAUNCH_CHECK();
+    if (trace) {
+        std::vector<u32> lv_h(np);
+        std::vector<i64> eo_h(np + 1);
+        std::vector<u64> wk_h(np);
+        PBNG_HIP(hipMemcpyAsync(lv_h.data(), fa.levels, sizeof(u32) * np, hipMemcpyDeviceToHost, s));
+        PBNG_HIP(hipMemcpyAsync(eo_h.data(), epoff, sizeof(i64) * (np + 1), hipMemcpyDeviceToHost, s));
+        PBNG_HIP(hipMemcpyAsync(wk_h.data(), work, sizeof(u64) * np, hipMemcpyDeviceToHost, s));
+        PBNG_HIP(hipStreamSynchronize(s));
+        for (int p = 0; p < np; ++p)
+            fprintf(stderr, "[pbng-trace] wing-fd part %d edges %lld levels %u work %llu\n", p, (long long)(eo_h[p + 1] - eo_h[p]),
+                    lv_h[p], (unsigned long long)wk_h[p]);
+    }
     c.stats.wedges_fd = read_scalar<u64>(c, fa.work);
     c.stats.ms_fd = wnow_ms() - t3;
     c.stats.wedges = c.stats.wedges_count + c.stats.links + c.stats.wedges_fd;
