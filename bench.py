@@ -70,6 +70,27 @@ def run_step(pb, ctx, dg, kind, P, flags):
     return outs, stats
 
 
+def copy_probe(torch, mib=1024, reps=5):
+    """Bandwidth of a plain elementwise copy kernel (int32 negate: mib MiB read,
+    mib MiB written per launch), timed with events on torch's stream.  Its
+    hardware byte counters calibrate those of the path's kernels."""
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        torch.neg(src, out=dst)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return dict(kernel="int32 negate", bytes_per_launch=2 * mib * (1 << 20), ms=round(ms, 4),
+                gbs=round(2 * mib * (1 << 20) / (ms / 1e3) / 1e9, 1))
+
+
 def cpu_baseline(graph_cfg, kind, budget_s):
     """The oracle on a bounded sample: the same generator family scaled down
     until one run takes about budget_s seconds on one host core."""
@@ -131,6 +152,8 @@ def main():
     ctx = pb.Context()
     dg = pb.DeviceGraph.from_graph(g)
     torch.cuda.synchronize()
+    copy = copy_probe(torch)
+    log(f"[bench] copy kernel: {copy['gbs']} GB/s")
 
     for i in range(args.warmup):
         run_step(pb, ctx, dg, kind, P, 0)
@@ -209,6 +232,7 @@ def main():
         "phases_ms": phases,
         "work": work,
         "roofline": roofline,
+        "copy_kernel": copy,
         "cpu_baseline": cpu,
         "parity_vs_oracle": parity or None,
     }

@@ -115,7 +115,11 @@ typedef struct {
     int32_t dense_cut;  /* degree above which hub pairs use the int8 matrix-
                            core path in counting; 0 = library default,
                            negative = never                                 */
-    int32_t reserved[3];
+    int32_t tile_w;     /* coarse-grained tip rounds: active vertices with
+                           more live wedges than this count in LDS key tiles,
+                           others in LDS hash ranges; 0 = library default
+                           (2^18), negative = never (schedule only)          */
+    int32_t reserved[2];
 } pbng_opts;
 
 /* Per-call counters and phase times of the last compute call. */

@@ -54,7 +54,8 @@ class Opts(ctypes.Structure):
         ("flags", ctypes.c_int32),
         ("seed", ctypes.c_int32),
         ("dense_cut", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 3),
+        ("tile_w", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 2),
     ]
 
 
@@ -145,9 +146,10 @@ def load():
     return lib
 
 
-def make_opts(P=0, bound_rule=BOUND_PLAIN, flags=0, seed=0, dense_cut=0) -> Opts:
+def make_opts(P=0, bound_rule=BOUND_PLAIN, flags=0, seed=0, dense_cut=0, tile_w=0) -> Opts:
     o = Opts()
     o.P, o.bound_rule, o.flags, o.seed, o.dense_cut = int(P), int(bound_rule), int(flags), int(seed), int(dense_cut)
+    o.tile_w = int(tile_w)
     return o
 
 

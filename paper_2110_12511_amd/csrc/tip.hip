@@ -63,7 +63,10 @@ constexpr u32 PULL_MIN_F = 0xFFFFFFFFu;
 // Heavy active vertices accumulate c(x, x') in LDS over key tiles of
 // 2^TILE_LOG consecutive X ids, two 16-bit counters per 32-bit word.
 constexpr int TILE_LOG = 16;
-constexpr i64 TB_LIMIT = i64(1) << 20;  // tile-boundary scratch per workgroup (ints)
+// active vertices with more wedges than this take the key-tile path
+constexpr i64 HUGE_W = i64(1) << 18;
+// LDS hash slots of the (vertex, key range) path
+constexpr int H_LOGCAP = 14;
 
 struct PeelArgs {
     const i64 *xrow;
@@ -83,8 +86,6 @@ struct PeelArgs {
     u32 *dcnt;
     i32 *dtouch;
     u32 *dntouch;
-    i32 *tbnd;           // tiled path: per-workgroup tile boundaries
-    i64 tbnd_stride;
     i32 ntiles;
     i64 nx;
     u64 *wedges;
@@ -104,6 +105,38 @@ struct ItemSmem {
 // a support that crosses below the bound puts x' in the next active set
 // (exactly once: supports only decrease).  Keys that are not alive (other
 // active vertices) are dropped in that epilogue, once per key.
+// Support updates of a batch of NB (key, count) pairs: the state loads and
+// the atomics of the batch are issued back to back so their latencies
+// overlap.  Keys < 0 or counts < 2 are skipped; so are vertices that are not
+// alive (peeled earlier or active this round).  A vertex whose support
+// crosses below the bound joins the next active set.
+template <int NB>
+__device__ __forceinline__ void apply_updates(const PeelArgs &a, u64 B, const i32 (&key)[NB], const u32 (&cnt)[NB],
+                                              Tally &t) {
+    bool ok[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) ok[q] = key[q] >= 0 && cnt[q] >= 2;
+#pragma unroll
+    for (int q = 0; q < NB; ++q)
+        if (ok[q]) ok[q] = a.st[key[q]] == ST_ALIVE;
+    u64 old[NB], dd[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        dd[q] = (u64)cnt[q] * (u64)(cnt[q] - 1) / 2;
+        old[q] = 0;
+        if (ok[q]) old[q] = atomicAdd((unsigned long long *)&a.sup[key[q]], (unsigned long long)(0ull - dd[q]));
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        if (!ok[q]) continue;
+        ++t.atomics;
+        if (old[q] >= B && old[q] - dd[q] < B) {
+            const u32 p = atomicAdd(a.nnf, 1u);
+            a.nf[p] = key[q];
+        }
+    }
+}
+
 template <int BLOCK, class Acc>
 __device__ __forceinline__ void peel_item(const PeelArgs &a, i32 x, Acc &A, const ItemSmem &sm, Tally &t) {
     const i64 jb = a.xrow[x], je = a.xrow[x + 1];
@@ -144,20 +177,18 @@ __device__ __forceinline__ void peel_item(const PeelArgs &a, i32 x, Acc &A, cons
     const i64 ne = sm.bcast[0];
     __syncthreads();
     const u64 B = *a.bound;
-    for (i64 i = threadIdx.x; i < ne; i += BLOCK) {
-        i32 key;
-        u32 c32;
-        A.entry(i, key, c32);
-        if (key < 0 || c32 < 2) continue;
-        if (a.st[key] != ST_ALIVE) continue;
-        u64 cc = c32;
-        u64 d = cc * (cc - 1) / 2;
-        u64 old = atomicAdd((unsigned long long *)&a.sup[key], (unsigned long long)(0ull - d));
-        ++t.atomics;
-        if (old >= B && old - d < B) {
-            u32 p = atomicAdd(a.nnf, 1u);
-            a.nf[p] = key;
+    constexpr int NB = 4;
+    for (i64 i0 = threadIdx.x; i0 < ne; i0 += (i64)NB * BLOCK) {
+        i32 key[NB];
+        u32 c32[NB];
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            const i64 i = i0 + (i64)q * BLOCK;
+            key[q] = -1;
+            c32[q] = 0;
+            if (i < ne) A.entry(i, key[q], c32[q]);
         }
+        apply_updates<NB>(a, B, key, c32, t);
     }
     __syncthreads();
 }
@@ -226,114 +257,316 @@ __global__ __launch_bounds__(256) void k_tip_peel_dense(PeelArgs a, int bin) {
 }
 
 // Heavy active vertices: the live Y lists are sorted by X id, so the wedges
-// of x whose far end lies in a key tile [r0, r0 + 2^TILE_LOG) form one run of
-// every list.  The run boundaries of all (neighbour, tile) pairs are found
-// once per vertex by binary search; then tile by tile the wedges are counted
-// in LDS (two 16-bit counters per word; a count never exceeds d_x < 2^16),
-// and the tile's counters are scanned for c >= 2.  No global atomic is issued
-// per wedge.
+// of x whose far end lies in a key tile [r0, r0 + 2^TLOG) form one run of
+// every list.  A work item is one (vertex, tile) pair, so the tiles of one
+// vertex run on different workgroups at once: each finds the run of every
+// neighbour's list by binary search, counts the run's wedges in LDS (two
+// 16-bit counters per word; a count never exceeds d_x < 2^16).  A counter
+// word that leaves zero sets its bit in a touched bitmap, and the epilogue
+// visits only the touched words, turning counts c >= 2 into updates.  Key
+// tiles are disjoint, so every (x, x') pair is completed by exactly one item.
+// No global atomic is issued per wedge.
 template <int TLOG>
 __global__ __launch_bounds__(512) void k_tip_peel_tiled(PeelArgs a, int bin) {
     constexpr int BLOCK = 512;
     constexpr int WORDS = (1 << TLOG) / 2;
+    constexpr int BWORDS = WORDS / 32;
     __shared__ u32 cnt[WORDS];
+    __shared__ u32 bm[BWORDS];
     __shared__ i32 s_pre[BLOCK];
     __shared__ i64 s_moff[BLOCK];
     __shared__ i32 s_wave[BLOCK / WAVE];
-    __shared__ i32 s_item;
+    __shared__ u32 s_item;
     for (int i = threadIdx.x; i < WORDS; i += BLOCK) cnt[i] = 0;
-    i32 *bnd = a.tbnd + (i64)blockIdx.x * a.tbnd_stride;
-    const u32 n = a.nitems[bin];
-    const i32 nt = a.ntiles;
+    for (int i = threadIdx.x; i < BWORDS; i += BLOCK) bm[i] = 0;
+    const u32 nt = (u32)a.ntiles;
+    const u64 n = (u64)a.nitems[bin] * nt;
     const u64 B = *a.bound;
     Tally tl;
     __syncthreads();
     for (;;) {
-        if (threadIdx.x == 0) s_item = (i32)atomicAdd(&a.next[bin], 1u);
+        if (threadIdx.x == 0) s_item = atomicAdd(&a.next[bin], 1u);
         __syncthreads();
-        const i32 item = s_item;
+        const u32 item = s_item;
         __syncthreads();
-        if ((u32)item >= n) break;
-        const i32 x = a.items[item];
+        if ((u64)item >= n) break;
+        const i32 x = a.items[item / nt];
+        const u32 t = item % nt;
+        const i64 r0 = (i64)t << TLOG;
+        const i64 r1 = r0 + (i64(1) << TLOG) < a.nx ? r0 + (i64(1) << TLOG) : a.nx;
         const i64 jb = a.xrow[x];
         const i32 d = (i32)(a.xrow[x + 1] - jb);
-        if (threadIdx.x == 0) {
+        if (threadIdx.x == 0 && t == 0) {
             tl.segments += (u64)d;
             tl.items += 1;
         }
-        // run boundaries: bnd[j * (nt + 1) + t] = first entry of list j with key >= t * 2^TLOG
-        const i32 nb = d * (nt + 1);
-        for (i32 q = threadIdx.x; q < nb; q += BLOCK) {
-            const i32 j = q / (nt + 1), t = q - j * (nt + 1);
-            const i32 y = a.xadj[jb + j];
-            const i64 base = a.yrow[y];
-            i64 lo = base, hi = base + a.ylen[y];
-            i64 r = (i64)t << TLOG;
-            if (r > a.nx) r = a.nx;
-            while (lo < hi) {
-                i64 md = (lo + hi) >> 1;
-                if ((i64)a.yadj[md] < r) lo = md + 1; else hi = md;
+        bool any = false;
+        for (i32 cb = 0; cb < d; cb += BLOCK) {
+            const i32 j = cb + threadIdx.x;
+            i32 pl = 0;
+            i64 moff = 0;
+            if (j < d) {
+                const i32 y = a.xadj[jb + j];
+                const i64 base = a.yrow[y];
+                const i64 end = base + a.ylen[y];
+                i64 lo = base, hi = end;
+                if (r0 > 0) {
+                    while (lo < hi) {
+                        const i64 md = (lo + hi) >> 1;
+                        if ((i64)a.yadj[md] < r0) lo = md + 1; else hi = md;
+                    }
+                }
+                i64 e = end;
+                if (r1 < a.nx) {
+                    i64 l2 = lo, h2 = end;
+                    while (l2 < h2) {
+                        const i64 md = (l2 + h2) >> 1;
+                        if ((i64)a.yadj[md] < r1) l2 = md + 1; else h2 = md;
+                    }
+                    e = l2;
+                }
+                pl = (i32)(e - lo);
+                moff = lo;
             }
-            st_coherent(&bnd[q], (i32)(lo - base));
+            i32 tot;
+            const i32 incl = block_incl_scan_i32<BLOCK>(pl, s_wave, tot);
+            if (tot == 0) continue;  // block-uniform
+            any = true;
+            s_pre[threadIdx.x] = incl;
+            s_moff[threadIdx.x] = moff;
+            __syncthreads();
+            for (i32 k = threadIdx.x; k < tot; k += BLOCK) {
+                int lo = 0, hi = BLOCK - 1;
+                while (lo < hi) {
+                    int md = (lo + hi) >> 1;
+                    if (s_pre[md] > k) hi = md; else lo = md + 1;
+                }
+                const i32 before = lo ? s_pre[lo - 1] : 0;
+                const i32 xp = a.yadj[s_moff[lo] + (k - before)];
+                if (xp == x) continue;
+                ++tl.wedges;
+                const i32 o = xp - (i32)r0;
+                const u32 wi = (u32)o >> 1;
+                if (atomicAdd(&cnt[wi], 1u << ((o & 1) << 4)) == 0u) atomicOr(&bm[wi >> 5], 1u << (wi & 31));
+            }
+            __syncthreads();
+        }
+        if (!any) continue;
+        const i32 nbw = (i32)(((r1 - r0 + 1) >> 1) + 31) >> 5;
+        for (i32 bw = threadIdx.x; bw < nbw; bw += BLOCK) {
+            u32 bits = bm[bw];
+            if (!bits) continue;
+            bm[bw] = 0;
+            while (bits) {
+                // up to four touched words (eight keys) per batch
+                i32 kk[8];
+                u32 cc[8];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    kk[2 * q] = kk[2 * q + 1] = -1;
+                    cc[2 * q] = cc[2 * q + 1] = 0;
+                    if (bits) {
+                        const i32 wi = bw * 32 + (__ffs(bits) - 1);
+                        bits &= bits - 1;
+                        const u32 v = cnt[wi];
+                        cnt[wi] = 0;
+                        cc[2 * q] = v & 0xFFFFu;
+                        cc[2 * q + 1] = v >> 16;
+                        kk[2 * q] = (i32)r0 + 2 * wi;
+                        kk[2 * q + 1] = (i32)r0 + 2 * wi + 1;
+                    }
+                }
+                apply_updates<8>(a, B, kk, cc, tl);
+            }
         }
         __syncthreads();
-        for (i32 t = 0; t < nt; ++t) {
-            const i32 r0 = t << TLOG;
-            bool any = false;
-            for (i32 cb = 0; cb < d; cb += BLOCK) {
-                const i32 j = cb + threadIdx.x;
-                i32 pl = 0;
-                i64 moff = 0;
-                if (j < d) {
-                    const i32 y = a.xadj[jb + j];
-                    const i32 b0 = ld_coherent(&bnd[j * (nt + 1) + t]);
-                    const i32 b1 = ld_coherent(&bnd[j * (nt + 1) + t + 1]);
-                    pl = b1 - b0;
-                    moff = a.yrow[y] + b0;
-                }
-                i32 tot;
-                const i32 incl = block_incl_scan_i32<BLOCK>(pl, s_wave, tot);
-                if (tot == 0) continue;  // block-uniform
-                any = true;
-                s_pre[threadIdx.x] = incl;
-                s_moff[threadIdx.x] = moff;
-                __syncthreads();
-                for (i32 k = threadIdx.x; k < tot; k += BLOCK) {
-                    int lo = 0, hi = BLOCK - 1;
-                    while (lo < hi) {
-                        int md = (lo + hi) >> 1;
-                        if (s_pre[md] > k) hi = md; else lo = md + 1;
+    }
+    tl.flush(a.kc, a.wedges);
+}
+
+// Heavy active vertices whose wedges are many but whose degree is small (a
+// few neighbours with long lists, the common case under power-law degrees):
+// the wedges of x are cut into R_x = ceil(w_x / H_RANGE_W) ranges of the X
+// key space, and one work item is one (vertex, range) pair.  Each range
+// counts c(x, x') in an LDS hash table of 2^LOGCAP slots; the run of every
+// neighbour list inside the range is found by binary search (none when
+// R_x = 1).  A key whose probe sequence is full goes, for every occurrence,
+// to the workgroup's HBM counters with a touched list, so every key lives
+// wholly in one of the two and the result is exact for any key skew.
+constexpr i64 H_RANGE_W = 10240;
+constexpr u32 H_RANGE_MAX = 64;
+constexpr int H_PROBE = 64;
+
+// R_x of every item of a bin and their exclusive prefix (one workgroup)
+__global__ __launch_bounds__(1024) void k_range_split(const i32 *items, const u32 *nbin, int bin, const u64 *wi, u32 *off,
+                                                      u32 *total) {
+    __shared__ i32 s_wave[1024 / WAVE];
+    const u32 n = nbin[bin];
+    u32 carry = 0;
+    for (u32 base = 0; base < n; base += 1024) {
+        const u32 i = base + threadIdx.x;
+        i32 r = 0;
+        if (i < n) {
+            const u64 w = wi[items[i]];
+            const u64 q = (w + (u64)H_RANGE_W - 1) / (u64)H_RANGE_W;
+            r = (i32)(q < 1 ? 1 : (q > H_RANGE_MAX ? H_RANGE_MAX : q));
+        }
+        i32 tot;
+        const i32 incl = block_incl_scan_i32<1024>(r, s_wave, tot);
+        if (i < n) off[i] = carry + (u32)(incl - r);
+        carry += (u32)tot;
+    }
+    if (threadIdx.x == 0) {
+        off[n] = carry;
+        *total = carry;
+    }
+}
+
+template <int LOGCAP>
+__global__ __launch_bounds__(512) void k_tip_peel_hrange(PeelArgs a, int bin, const u32 *off, const u32 *total) {
+    constexpr int BLOCK = 512;
+    constexpr u32 CAP = 1u << LOGCAP;
+    __shared__ i32 keys[CAP];
+    __shared__ u32 vals[CAP];
+    __shared__ i32 s_pre[BLOCK];
+    __shared__ i64 s_moff[BLOCK];
+    __shared__ i32 s_wave[BLOCK / WAVE];
+    __shared__ u32 s_item, s_ntouch;
+    for (u32 i = threadIdx.x; i < CAP; i += BLOCK) {
+        keys[i] = -1;
+        vals[i] = 0;
+    }
+    if (threadIdx.x == 0) s_ntouch = 0;
+    u32 *gc = a.dcnt + (i64)blockIdx.x * a.nx;
+    i32 *touch = a.dtouch + (i64)blockIdx.x * a.nx;
+    const u32 nh = a.nitems[bin];
+    const u32 n = *total;
+    const u64 B = *a.bound;
+    Tally tl;
+    __syncthreads();
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(&a.next[bin], 1u);
+        __syncthreads();
+        const u32 item = s_item;
+        __syncthreads();
+        if (item >= n) break;
+        // owning vertex: last h with off[h] <= item
+        u32 lo = 0, hi = nh - 1;
+        while (lo < hi) {
+            const u32 md = (lo + hi + 1) >> 1;
+            if (off[md] <= item) lo = md; else hi = md - 1;
+        }
+        const i32 x = a.items[lo];
+        const u32 r = item - off[lo];
+        const u32 R = off[lo + 1] - off[lo];
+        const i64 k0 = (i64)r * a.nx / R, k1 = (i64)(r + 1) * a.nx / R;
+        const i64 jb = a.xrow[x];
+        const i32 d = (i32)(a.xrow[x + 1] - jb);
+        if (threadIdx.x == 0 && r == 0) {
+            tl.segments += (u64)d;
+            tl.items += 1;
+        }
+        for (i32 cb = 0; cb < d; cb += BLOCK) {
+            const i32 j = cb + threadIdx.x;
+            i32 pl = 0;
+            i64 moff = 0;
+            if (j < d) {
+                const i32 y = a.xadj[jb + j];
+                const i64 base = a.yrow[y];
+                const i64 end = base + a.ylen[y];
+                i64 b0 = base, e = end;
+                if (k0 > 0) {
+                    i64 h2 = end;
+                    while (b0 < h2) {
+                        const i64 md = (b0 + h2) >> 1;
+                        if ((i64)a.yadj[md] < k0) b0 = md + 1; else h2 = md;
                     }
-                    const i32 before = lo ? s_pre[lo - 1] : 0;
-                    const i32 xp = a.yadj[s_moff[lo] + (k - before)];
-                    if (xp == x) continue;
-                    ++tl.wedges;
-                    const i32 o = xp - r0;
-                    atomicAdd(&cnt[o >> 1], 1u << ((o & 1) << 4));
                 }
-                __syncthreads();
+                if (k1 < a.nx) {
+                    i64 l2 = b0;
+                    while (l2 < e) {
+                        const i64 md = (l2 + e) >> 1;
+                        if ((i64)a.yadj[md] < k1) l2 = md + 1; else e = md;
+                    }
+                }
+                pl = (i32)(e - b0);
+                moff = b0;
             }
-            if (!any) continue;
-            for (i32 wi = threadIdx.x; wi < WORDS; wi += BLOCK) {
-                const u32 v = cnt[wi];
-                if (!v) continue;
-                cnt[wi] = 0;
-                for (int h = 0; h < 2; ++h) {
-                    const u64 cc = (v >> (16 * h)) & 0xFFFFu;
-                    if (cc < 2) continue;
-                    const i32 xp = r0 + 2 * wi + h;
-                    if (a.st[xp] != ST_ALIVE) continue;
-                    const u64 dd = cc * (cc - 1) / 2;
-                    const u64 old = atomicAdd((unsigned long long *)&a.sup[xp], (unsigned long long)(0ull - dd));
-                    ++tl.atomics;
-                    if (old >= B && old - dd < B) {
-                        u32 p = atomicAdd(a.nnf, 1u);
-                        a.nf[p] = xp;
+            i32 tot;
+            const i32 incl = block_incl_scan_i32<BLOCK>(pl, s_wave, tot);
+            if (tot == 0) continue;  // block-uniform
+            s_pre[threadIdx.x] = incl;
+            s_moff[threadIdx.x] = moff;
+            __syncthreads();
+            const int last = (d - cb < BLOCK ? d - cb : BLOCK) - 1;
+            for (i32 k = threadIdx.x; k < tot; k += BLOCK) {
+                int l = 0, h = last;
+                while (l < h) {
+                    const int md = (l + h) >> 1;
+                    if (s_pre[md] > k) h = md; else l = md + 1;
+                }
+                const i32 before = l ? s_pre[l - 1] : 0;
+                const i32 xp = a.yadj[s_moff[l] + (k - before)];
+                if (xp == x) continue;
+                ++tl.wedges;
+                u32 hs = hash32((u32)xp) >> (32 - LOGCAP);
+                bool done = false;
+                for (int p = 0; p < H_PROBE; ++p) {
+                    const i32 kk = keys[hs];
+                    if (kk == xp) {
+                        done = true;
+                        break;
+                    }
+                    if (kk == -1) {
+                        const i32 prev = atomicCAS(&keys[hs], -1, xp);
+                        if (prev == -1 || prev == xp) {
+                            done = true;
+                            break;
+                        }
+                    }
+                    hs = (hs + 1) & (CAP - 1);
+                }
+                if (done) {
+                    atomicAdd(&vals[hs], 1u);
+                } else {
+                    const u32 old = __hip_atomic_fetch_add(&gc[xp], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (old == 0) {
+                        const u32 t = atomicAdd(&s_ntouch, 1u);
+                        __hip_atomic_store(&touch[t], xp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     }
                 }
             }
             __syncthreads();
         }
+        // epilogue: LDS entries, then keys that overflowed to HBM
+        constexpr int NB = 8;
+        for (u32 i0 = threadIdx.x; i0 < CAP; i0 += NB * BLOCK) {
+            i32 kk[NB];
+            u32 cc[NB];
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                const u32 i = i0 + q * BLOCK;
+                kk[q] = keys[i];
+                cc[q] = vals[i];
+                keys[i] = -1;
+                vals[i] = 0;
+            }
+            apply_updates<NB>(a, B, kk, cc, tl);
+        }
+        const u32 nt = s_ntouch;
+        for (u32 i0 = threadIdx.x; i0 < nt; i0 += 4 * BLOCK) {
+            i32 kk[4];
+            u32 cc[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const u32 i = i0 + q * BLOCK;
+                kk[q] = i < nt ? __hip_atomic_load(&touch[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : -1;
+                cc[q] = kk[q] >= 0 ? __hip_atomic_exchange(&gc[kk[q]], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+            }
+            apply_updates<4>(a, B, kk, cc, tl);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) s_ntouch = 0;
     }
     tl.flush(a.kc, a.wedges);
 }
@@ -693,7 +926,7 @@ __global__ __launch_bounds__(256) void k_pull_dense(PullArgs a, int bin) {
 // their total (the batch rule's wedge count of the active set, Section 5.1),
 // and the work bins: small / medium LDS hash, LDS key tiles, HBM counters.
 __global__ void k_item_work(const i32 *F, const u32 *nF, const i64 *xrow, const i32 *xadj, const i32 *ylen, u64 *wi,
-                            u64 *wsum, i32 *lists, i64 stride, u32 *nbin, int heavy_bin) {
+                            u64 *wsum, i32 *lists, i64 stride, u32 *nbin, u64 huge_w) {
     const int lane = threadIdx.x & (WAVE - 1);
     const i64 wave = (blockIdx.x * (i64)blockDim.x + threadIdx.x) / WAVE;
     const i64 nwaves = (i64)gridDim.x * blockDim.x / WAVE;
@@ -711,7 +944,8 @@ __global__ void k_item_work(const i32 *F, const u32 *nF, const i64 *xrow, const 
                 int b;
                 if (s <= (u64)T_SMALL_W) b = 0;
                 else if (s <= (u64)T_MEDIUM_W) b = 1;
-                else b = heavy_bin;
+                else if (s <= huge_w) b = 2;
+                else b = 3;
                 u32 p = atomicAdd(&nbin[b], 1u);
                 lists[b * stride + p] = x;
             }
@@ -1243,14 +1477,17 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
     // LDS key tiles for heavy active vertices (one 512-lane workgroup per CU)
     const i32 ntiles = (i32)((nx + (i64(1) << TILE_LOG) - 1) >> TILE_LOG);
     const int tslots = c.num_cu;
-    i32 *tbnd = c.alloc<i32>((i64)tslots * TB_LIMIT);
-    // heavy vertices stream into HBM counters with an LDS touched bitmap when
-    // one bit per X vertex fits in LDS
+    // Active vertices above HUGE_W wedges use LDS key tiles while the X side
+    // has at most 2^20 vertices (16 tiles); streaming into HBM counters with
+    // an LDS touched bitmap is the alternative (PBNG_HEAVY=b) while one bit per
+    // X vertex fits in LDS; beyond that, HBM counters with a touched list.
     constexpr int BITS_NBW = 1 << 15;
-    const int heavy_bin = nx <= (i64)BITS_NBW * 32 ? 2 : 3;
-    // heavy-vertex strategy: LDS key tiles (default) or HBM-counter streaming
     const char *heavy_env = getenv("PBNG_HEAVY");
-    const bool heavy_tiled = !(heavy_env && heavy_env[0] == 'b');
+    const bool huge_bits = heavy_env && heavy_env[0] == 'b' && nx <= (i64)BITS_NBW * 32;
+    const bool huge_tiled = !huge_bits && nx <= (i64(1) << 20);
+    const u64 huge_w = o.tile_w == 0 ? (u64)HUGE_W : (o.tile_w < 0 ? ~0ull : (u64)o.tile_w);
+    u32 *hoff = c.alloc<u32>(nx + 1);
+    u32 *htotal = c.alloc<u32>(1);
     const char *pull_env = getenv("PBNG_PULL_MIN_F");
     const u32 pull_min_f = pull_env ? (u32)atol(pull_env) : PULL_MIN_F;
     // pull rounds: active lists of touched Y vertices, receivers
@@ -1301,8 +1538,6 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
     pa.dcnt = dcnt;
     pa.dtouch = dtouch;
     pa.dntouch = dntouch;
-    pa.tbnd = tbnd;
-    pa.tbnd_stride = TB_LIMIT;
     pa.ntiles = ntiles;
     pa.nx = nx;
     pa.wedges = &ctl->wedges;
@@ -1322,7 +1557,7 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
     auto item_work = [&](i32 *cur) {
         hipLaunchKernelGGL(k_item_work, dim3(grid_1d((i64)nx * WAVE)), dim3(256), 0, s, (const i32 *)cur,
                            (const u32 *)&ctl->nF, xrow, xadj, (const i32 *)ylen, wi, &ctl->wF, bins, nx, ctl->nbin,
-                           heavy_bin);
+                           huge_w);
         PBNG_LAUNCH_CHECK();
     };
     while (n_alive > 0) {
@@ -1438,11 +1673,17 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
                 PeelArgs pm = pa;
                 pm.items = bins + nx;
                 c.kbegin(PBNG_K_TIP_PEEL);
-                hipLaunchKernelGGL(k_tip_peel_dense, dim3(std::min<i64>(slots, nF)), dim3(256), 0, s, pd, 3);
-                if (heavy_bin == 2 && heavy_tiled)
-                    hipLaunchKernelGGL(k_tip_peel_tiled<TILE_LOG>, dim3(std::min<i64>(tslots, nF)), dim3(512), 0, s, pt, 2);
-                else if (heavy_bin == 2)
-                    hipLaunchKernelGGL(k_tip_peel_bits<BITS_NBW>, dim3(std::min<i64>(slots, nF)), dim3(512), 0, s, pt, 2);
+                if (huge_tiled)
+                    hipLaunchKernelGGL(k_tip_peel_tiled<TILE_LOG>, dim3(std::min<i64>(tslots, (i64)nF * ntiles)), dim3(512), 0, s,
+                                       pd, 3);
+                else if (huge_bits)
+                    hipLaunchKernelGGL(k_tip_peel_bits<BITS_NBW>, dim3(std::min<i64>(slots, nF)), dim3(512), 0, s, pd, 3);
+                else
+                    hipLaunchKernelGGL(k_tip_peel_dense, dim3(std::min<i64>(slots, nF)), dim3(256), 0, s, pd, 3);
+                hipLaunchKernelGGL(k_range_split, dim3(1), dim3(1024), 0, s, (const i32 *)pt.items, (const u32 *)ctl->nbin, 2,
+                                   (const u64 *)wi, hoff, htotal);
+                hipLaunchKernelGGL(k_tip_peel_hrange<H_LOGCAP>, dim3(std::min<i64>(slots, (i64)nF * H_RANGE_MAX)), dim3(512), 0,
+                                   s, pt, 2, (const u32 *)hoff, (const u32 *)htotal);
                 hipLaunchKernelGGL((k_tip_peel_hash<256, 13>), dim3(std::min<i64>((i64)c.num_cu * 2, nF)), dim3(256), 0, s, pm, 1);
                 hipLaunchKernelGGL((k_tip_peel_hash<64, 10>), dim3(std::min<i64>((i64)c.num_cu * 16, nF)), dim3(64), 0, s, pa, 0);
                 c.kend(PBNG_K_TIP_PEEL);

@@ -116,3 +116,41 @@ def test_tip_dense_tile_cutovers(ctx, cl_mid, cut):
     g, eu, ev = cl_mid
     assert np.array_equal(gpu_tip(ctx, g, 0, P=150, dense_cut=cut), eu)
     assert np.array_equal(gpu_tip(ctx, g, 1, P=150, dense_cut=cut), ev)
+
+
+@pytest.mark.parametrize("tile_w", [-1, 1, 5000, 100000])
+def test_tip_heavy_paths(ctx, cl_mid, tile_w):
+    """Key tiles vs LDS hash ranges for the heavy active vertices: same result."""
+    g, eu, ev = cl_mid
+    assert np.array_equal(gpu_tip(ctx, g, 0, P=150, tile_w=tile_w), eu)
+    assert np.array_equal(gpu_tip(ctx, g, 1, P=150, tile_w=tile_w), ev)
+
+
+def clustered_graph(seed=7):
+    """Three hubs over overlapping blocks of ~17k consecutive U ids plus sparse
+    extras: the 2-hop keys of a block vertex crowd one key range, more than an
+    LDS hash range holds, so keys spill to the HBM counters."""
+    rng = np.random.default_rng(seed)
+    n_u, n_v = 200000, 64
+    edges = set()
+    for v, (a, b) in enumerate([(0, 17000), (500, 17500), (1000, 18000)]):
+        for u in range(a, b):
+            edges.add((u, v))
+    for u in range(0, 20000):
+        for v in rng.choice(np.arange(3, n_v), size=int(rng.integers(0, 4)), replace=False):
+            edges.add((u, int(v)))
+    for u in rng.integers(20000, n_u, 3000):
+        edges.add((int(u), int(rng.integers(3, n_v))))
+    return synth.from_edges(n_u, n_v, sorted(edges))
+
+
+@pytest.fixture(scope="module")
+def clustered():
+    g = clustered_graph()
+    return g, oracle.tip(g, 0)
+
+
+@pytest.mark.parametrize("P,tile_w", [(1, 0), (8, 0), (40, 0), (40, -1), (40, 5000)])
+def test_tip_clustered_keys_overflow(ctx, clustered, P, tile_w):
+    g, eu = clustered
+    assert np.array_equal(gpu_tip(ctx, g, 0, P=P, tile_w=tile_w), eu)
