@@ -335,19 +335,33 @@ __global__ __launch_bounds__(512) void k_tip_peel_tiled(PeelArgs a, int bin) {
             s_pre[threadIdx.x] = incl;
             s_moff[threadIdx.x] = moff;
             __syncthreads();
-            for (i32 k = threadIdx.x; k < tot; k += BLOCK) {
-                int lo = 0, hi = BLOCK - 1;
-                while (lo < hi) {
-                    int md = (lo + hi) >> 1;
-                    if (s_pre[md] > k) hi = md; else lo = md + 1;
+            const int last = (d - cb < BLOCK ? d - cb : BLOCK) - 1;
+            constexpr int UN = 4;
+            for (i32 k0 = threadIdx.x; k0 < tot; k0 += UN * BLOCK) {
+                i32 xq[UN];
+#pragma unroll
+                for (int q = 0; q < UN; ++q) {
+                    const i32 k = k0 + q * BLOCK;
+                    xq[q] = x;
+                    if (k < tot) {
+                        int lo = 0, hi = last;
+                        while (lo < hi) {
+                            int md = (lo + hi) >> 1;
+                            if (s_pre[md] > k) hi = md; else lo = md + 1;
+                        }
+                        const i32 before = lo ? s_pre[lo - 1] : 0;
+                        xq[q] = a.yadj[s_moff[lo] + (k - before)];
+                    }
                 }
-                const i32 before = lo ? s_pre[lo - 1] : 0;
-                const i32 xp = a.yadj[s_moff[lo] + (k - before)];
-                if (xp == x) continue;
-                ++tl.wedges;
-                const i32 o = xp - (i32)r0;
-                const u32 wi = (u32)o >> 1;
-                if (atomicAdd(&cnt[wi], 1u << ((o & 1) << 4)) == 0u) atomicOr(&bm[wi >> 5], 1u << (wi & 31));
+#pragma unroll
+                for (int q = 0; q < UN; ++q) {
+                    const i32 xp = xq[q];
+                    if (xp == x) continue;
+                    ++tl.wedges;
+                    const i32 o = xp - (i32)r0;
+                    const u32 wi = (u32)o >> 1;
+                    if (atomicAdd(&cnt[wi], 1u << ((o & 1) << 4)) == 0u) atomicOr(&bm[wi >> 5], 1u << (wi & 31));
+                }
             }
             __syncthreads();
         }
@@ -499,14 +513,27 @@ __global__ __launch_bounds__(512) void k_tip_peel_hrange(PeelArgs a, int bin, co
             s_moff[threadIdx.x] = moff;
             __syncthreads();
             const int last = (d - cb < BLOCK ? d - cb : BLOCK) - 1;
-            for (i32 k = threadIdx.x; k < tot; k += BLOCK) {
-                int l = 0, h = last;
-                while (l < h) {
-                    const int md = (l + h) >> 1;
-                    if (s_pre[md] > k) h = md; else l = md + 1;
+            constexpr int UN = 4;
+            for (i32 k0 = threadIdx.x; k0 < tot; k0 += UN * BLOCK) {
+                // the far ends of UN wedges are loaded together
+                i32 xq[UN];
+#pragma unroll
+                for (int q = 0; q < UN; ++q) {
+                    const i32 k = k0 + q * BLOCK;
+                    xq[q] = x;
+                    if (k < tot) {
+                        int l = 0, h = last;
+                        while (l < h) {
+                            const int md = (l + h) >> 1;
+                            if (s_pre[md] > k) h = md; else l = md + 1;
+                        }
+                        const i32 before = l ? s_pre[l - 1] : 0;
+                        xq[q] = a.yadj[s_moff[l] + (k - before)];
+                    }
                 }
-                const i32 before = l ? s_pre[l - 1] : 0;
-                const i32 xp = a.yadj[s_moff[l] + (k - before)];
+#pragma unroll
+                for (int q = 0; q < UN; ++q) {
+                const i32 xp = xq[q];
                 if (xp == x) continue;
                 ++tl.wedges;
                 u32 hs = hash32((u32)xp) >> (32 - LOGCAP);
@@ -534,6 +561,7 @@ __global__ __launch_bounds__(512) void k_tip_peel_hrange(PeelArgs a, int bin, co
                         const u32 t = atomicAdd(&s_ntouch, 1u);
                         __hip_atomic_store(&touch[t], xp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     }
+                }
                 }
             }
             __syncthreads();
