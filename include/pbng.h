@@ -136,6 +136,8 @@ typedef struct {
     uint64_t recounts;        /* tip rounds done by recounting (Section 5.1) */
     int32_t partitions;       /* partitions actually created                 */
     int32_t P_used;           /* partitions requested after clamping         */
+    int32_t bound_rule_used;  /* pbng_bound_rule the call actually used      */
+    int32_t reserved_i;
     uint64_t fd_work_max, fd_work_sum; /* estimated fine-grained work        */
     uint64_t dense_pairs;     /* hub pairs counted on matrix cores           */
     pbng_kernel_stat kstat[PBNG_K_NCLASS];
@@ -162,6 +164,56 @@ int pbng_tip(pbng_ctx *ctx, const pbng_csr *g, pbng_side side,
  * wing_out: uint64[m].  opts may be NULL.                                 */
 int pbng_wing(pbng_ctx *ctx, const pbng_csr *g, const pbng_opts *opts,
               uint64_t *wing_out);
+
+/* ---- Learned range bounds (Section 3.1.3 replaced by a predictor) -------
+ *
+ * The coarse-grained phase needs each partition's upper bound.  The paper
+ * picks it from current supports with a work estimate; PBNG_BOUND_LEARNED
+ * instead takes the work-weighted quantile of predicted tip numbers
+ * theta_hat = r_hat * support, where r_hat in [0, 1] is the output of a
+ * multilayer perceptron (8 inputs, three hidden layers of 64 ReLU units,
+ * sigmoid output; fp32) on per-vertex features.  Results never depend on the
+ * predictor: only the partition schedule does.
+ *
+ * Parameters: one flat float vector of PBNG_MLP_NPARAM entries laid out as
+ * W1[64][8], b1[64], W2[64][64], b2[64], W3[64][64], b3[64], w4[64], b4
+ * (row-major, output index first).  Features, 8 per vertex of one side, with
+ * d = degree, w = sum of neighbour degrees, dmax/dmin = largest/smallest
+ * neighbour degree, S = butterfly support, Smax/Wmax = maxima over the side,
+ * m = edges, L = natural log1p:
+ *   L(d)/8, L(S)/32, L(w)/16, L(dmax)/12, L(dmin)/12, L(S)/L(Smax),
+ *   L(w)/L(Wmax), L(m)/24   (0 for a vertex of degree 0, except the last;
+ *   0 where a divisor is 0).
+ * Training target: r = theta / S (0 when S = 0).  Loss: sum wt (r_hat - r)^2
+ * / sum wt.  Optimiser: Adam (beta1 0.9, beta2 0.999, eps 1e-8) with bias
+ * correction; one step per minibatch, rows in the order given.
+ *
+ * The parameters and Adam state belong to the context; the calls below run
+ * on the context's stream and return when done.                            */
+#define PBNG_MLP_NPARAM 8961
+
+/* Features of every vertex of one side: feat[n_side * 8] (row-major), in the
+ * same memory space as the graph.                                          */
+int pbng_tip_features(pbng_ctx *ctx, const pbng_csr *g, pbng_side side,
+                      float *feat);
+/* He-uniform weights and zero biases from a seed; Adam state cleared.     */
+int pbng_mlp_init(pbng_ctx *ctx, uint64_t seed);
+/* Copy parameters in from / out to host memory (PBNG_MLP_NPARAM floats);
+ * set clears the Adam state.  get fails with PBNG_E_ARG before any init.  */
+int pbng_mlp_set(pbng_ctx *ctx, const float *params);
+int pbng_mlp_get(pbng_ctx *ctx, float *params);
+/* r_hat for n rows of x (device [n * 8]) into y (device [n]).            */
+int pbng_mlp_forward(pbng_ctx *ctx, const float *x, int64_t n, float *y);
+/* Loss and gradient over n rows (device x [n*8], r [n], wt [n]); grad is
+ * device [PBNG_MLP_NPARAM], loss a host float.                             */
+int pbng_mlp_loss_grad(pbng_ctx *ctx, const float *x, const float *r,
+                       const float *wt, int64_t n, float *grad, float *loss);
+/* epochs passes of minibatch Adam over n rows (device pointers) with the
+ * given batch size and learning rate; epoch_loss (host [epochs], may be
+ * NULL) receives each epoch's mean loss as the epoch went.                 */
+int pbng_mlp_train(pbng_ctx *ctx, const float *x, const float *r,
+                   const float *wt, int64_t n, int32_t batch, int32_t epochs,
+                   float lr, float *epoch_loss);
 
 #ifdef __cplusplus
 }

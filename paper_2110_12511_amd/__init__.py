@@ -23,6 +23,7 @@ from .binding import (  # noqa: F401
     host_csr,
     make_opts,
     tip,
+    tip_features,
     to_numpy_u64,
     wing,
     load,

@@ -93,6 +93,8 @@ class Stats(ctypes.Structure):
         ("recounts", ctypes.c_uint64),
         ("partitions", ctypes.c_int32),
         ("P_used", ctypes.c_int32),
+        ("bound_rule_used", ctypes.c_int32),
+        ("reserved_i", ctypes.c_int32),
         ("fd_work_max", ctypes.c_uint64),
         ("fd_work_sum", ctypes.c_uint64),
         ("dense_pairs", ctypes.c_uint64),
@@ -109,7 +111,10 @@ class Stats(ctypes.Structure):
         return d
 
 
-EXPORTS = ["pbng_create", "pbng_destroy", "pbng_last_error", "pbng_last_stats", "pbng_count", "pbng_tip", "pbng_wing"]
+EXPORTS = ["pbng_create", "pbng_destroy", "pbng_last_error", "pbng_last_stats", "pbng_count", "pbng_tip", "pbng_wing",
+           "pbng_tip_features", "pbng_mlp_init", "pbng_mlp_set", "pbng_mlp_get", "pbng_mlp_forward",
+           "pbng_mlp_loss_grad", "pbng_mlp_train"]
+MLP_NPARAM = 8961
 
 _lib = None
 
@@ -142,6 +147,20 @@ def load():
     lib.pbng_tip.restype = ctypes.c_int
     lib.pbng_wing.argtypes = [vp, ctypes.POINTER(Csr), ctypes.POINTER(Opts), vp]
     lib.pbng_wing.restype = ctypes.c_int
+    i64, f32 = ctypes.c_int64, ctypes.c_float
+    sigs = {
+        "pbng_tip_features": [vp, ctypes.POINTER(Csr), ctypes.c_int, vp],
+        "pbng_mlp_init": [vp, ctypes.c_uint64],
+        "pbng_mlp_set": [vp, vp],
+        "pbng_mlp_get": [vp, vp],
+        "pbng_mlp_forward": [vp, vp, i64, vp],
+        "pbng_mlp_loss_grad": [vp, vp, vp, vp, i64, vp, vp],
+        "pbng_mlp_train": [vp, vp, vp, vp, i64, ctypes.c_int32, ctypes.c_int32, f32, vp],
+    }
+    for name, args in sigs.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -196,6 +215,47 @@ class Context:
         self._check(self.lib.pbng_wing(self.h, ctypes.byref(csr), ctypes.byref(opts) if opts else None,
                                        ctypes.c_void_p(out_ptr)))
 
+    # learned range-bound predictor ----------------------------------------
+    def mlp_init(self, seed: int = 0):
+        self._check(self.lib.pbng_mlp_init(self.h, ctypes.c_uint64(int(seed))))
+
+    def mlp_set(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.shape != (MLP_NPARAM,):
+            raise ValueError(f"expected {MLP_NPARAM} parameters, got {p.shape}")
+        self._check(self.lib.pbng_mlp_set(self.h, p.ctypes.data))
+
+    def mlp_get(self) -> np.ndarray:
+        p = np.zeros(MLP_NPARAM, dtype=np.float32)
+        self._check(self.lib.pbng_mlp_get(self.h, p.ctypes.data))
+        return p
+
+    def mlp_forward(self, x):
+        """r_hat for the rows of a float32 cuda tensor [n, 8]."""
+        import torch
+
+        x = x.contiguous()
+        y = torch.empty(max(x.shape[0], 1), dtype=torch.float32, device=x.device)
+        self._check(self.lib.pbng_mlp_forward(self.h, x.data_ptr(), x.shape[0], y.data_ptr()))
+        return y[: x.shape[0]]
+
+    def mlp_loss_grad(self, x, r, wt):
+        import torch
+
+        x, r, wt = x.contiguous(), r.contiguous(), wt.contiguous()
+        g = torch.empty(MLP_NPARAM, dtype=torch.float32, device=x.device)
+        loss = ctypes.c_float()
+        self._check(self.lib.pbng_mlp_loss_grad(self.h, x.data_ptr(), r.data_ptr(), wt.data_ptr(), x.shape[0],
+                                                g.data_ptr(), ctypes.byref(loss)))
+        return float(loss.value), g
+
+    def mlp_train(self, x, r, wt, batch=4096, epochs=1, lr=1e-3):
+        x, r, wt = x.contiguous(), r.contiguous(), wt.contiguous()
+        out = np.zeros(max(int(epochs), 1), dtype=np.float32)
+        self._check(self.lib.pbng_mlp_train(self.h, x.data_ptr(), r.data_ptr(), wt.data_ptr(), x.shape[0], int(batch),
+                                            int(epochs), ctypes.c_float(lr), out.ctypes.data))
+        return out[: int(epochs)]
+
 
 # ---------------------------------------------------------------- graphs
 
@@ -249,6 +309,16 @@ def tip(ctx: Context, dg: DeviceGraph, side: int, opts: Opts | None = None):
     n = dg.n_u if side == SIDE_U else dg.n_v
     out = _out_tensor(n)
     ctx.tip_raw(dg.csr(), side, out.data_ptr(), opts)
+    return out[:n]
+
+
+def tip_features(ctx: Context, dg: DeviceGraph, side: int):
+    """The predictor's 8 features of every vertex of one side (float32 [n, 8])."""
+    import torch
+
+    n = dg.n_u if side == SIDE_U else dg.n_v
+    out = torch.zeros((max(n, 1), 8), dtype=torch.float32, device="cuda")
+    ctx._check(ctx.lib.pbng_tip_features(ctx.h, ctypes.byref(dg.csr()), side, ctypes.c_void_p(out.data_ptr())))
     return out[:n]
 
 

@@ -121,6 +121,14 @@ int pbng_create(pbng_ctx **out, void *stream) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, x->c.device) == hipSuccess && prop.multiProcessorCount > 0)
         x->c.num_cu = prop.multiProcessorCount;
+    // per-class work counters: every traversal kernel adds to them, so they
+    // exist for the context's whole life
+    if (hipMalloc(&x->c.kctr, sizeof(KCounters) * PBNG_K_NCLASS) != hipSuccess ||
+        hipMemset(x->c.kctr, 0, sizeof(KCounters) * PBNG_K_NCLASS) != hipSuccess) {
+        if (x->c.kctr) (void)hipFree(x->c.kctr);
+        delete x;
+        return PBNG_E_DEVICE;
+    }
     *out = x;
     return PBNG_OK;
 }
@@ -131,6 +139,7 @@ void pbng_destroy(pbng_ctx *x) {
     x->c.arena.destroy();
     if (x->c.sel_scratch) (void)hipFree(x->c.sel_scratch);
     if (x->c.kctr) (void)hipFree(x->c.kctr);
+    if (x->c.mlp_p) (void)hipFree(x->c.mlp_p);
     for (hipEvent_t e : x->c.ev_pool) (void)hipEventDestroy(e);
     delete x;
 }
@@ -228,6 +237,70 @@ int pbng_wing(pbng_ctx *x, const pbng_csr *g, const pbng_opts *opts, uint64_t *w
         if (o.flags & PBNG_F_KERNEL_TIMING) c.timing_end_call();
         c.stats.ms_total = ms_since(t0);
     });
+}
+
+int pbng_tip_features(pbng_ctx *x, const pbng_csr *g, pbng_side side, float *feat) {
+    if (!x) return PBNG_E_ARG;
+    Ctx &c = x->c;
+    int rc = check_csr(g);
+    if (rc) return fail(c, rc, "bad graph arguments");
+    if (side != PBNG_SIDE_U && side != PBNG_SIDE_V) return fail(c, PBNG_E_ARG, "bad side");
+    const i64 nx = side == PBNG_SIDE_U ? g->n_u : g->n_v;
+    if (nx > 0 && !feat) return fail(c, PBNG_E_ARG, "null output");
+    CallScope scope(c);
+    return guarded(c, [&] {
+        c.timing_begin_call(false);
+        pbng_csr dg = device_graph(c, *g);
+        DevGraph G;
+        build_graph(c, dg, G);
+        u64 *sup = c.alloc<u64>(nx);
+        count_side(c, G, side, pbng_opts{}, sup);
+        float *F = g->on_device ? feat : c.alloc<float>(nx * 8);
+        tip_features(c, G, side, sup, F);
+        if (!g->on_device && nx)
+            PBNG_HIP(hipMemcpyAsync(feat, F, sizeof(float) * nx * 8, hipMemcpyDeviceToHost, c.stream));
+        PBNG_HIP(hipStreamSynchronize(c.stream));
+    });
+}
+
+int pbng_mlp_init(pbng_ctx *x, uint64_t seed) {
+    if (!x) return PBNG_E_ARG;
+    return guarded(x->c, [&] { mlp_init(x->c, seed); });
+}
+
+int pbng_mlp_set(pbng_ctx *x, const float *params) {
+    if (!x || !params) return PBNG_E_ARG;
+    return guarded(x->c, [&] { mlp_set(x->c, params); });
+}
+
+int pbng_mlp_get(pbng_ctx *x, float *params) {
+    if (!x || !params) return PBNG_E_ARG;
+    return guarded(x->c, [&] { mlp_get(x->c, params); });
+}
+
+int pbng_mlp_forward(pbng_ctx *x, const float *in, int64_t n, float *out) {
+    if (!x || n < 0 || (n > 0 && (!in || !out))) return PBNG_E_ARG;
+    Ctx &c = x->c;
+    return guarded(c, [&] {
+        mlp_forward(c, in, n, out);
+        PBNG_HIP(hipStreamSynchronize(c.stream));
+    });
+}
+
+int pbng_mlp_loss_grad(pbng_ctx *x, const float *in, const float *r, const float *wt, int64_t n, float *grad,
+                       float *loss) {
+    if (!x || n < 0 || !grad || !loss || (n > 0 && (!in || !r || !wt))) return PBNG_E_ARG;
+    Ctx &c = x->c;
+    CallScope scope(c);
+    return guarded(c, [&] { mlp_loss_grad(c, in, r, wt, n, grad, loss); });
+}
+
+int pbng_mlp_train(pbng_ctx *x, const float *in, const float *r, const float *wt, int64_t n, int32_t batch,
+                   int32_t epochs, float lr, float *epoch_loss) {
+    if (!x || n < 0 || batch <= 0 || epochs < 0 || (n > 0 && (!in || !r || !wt))) return PBNG_E_ARG;
+    Ctx &c = x->c;
+    CallScope scope(c);
+    return guarded(c, [&] { mlp_train(c, in, r, wt, n, batch, epochs, lr, epoch_loss); });
 }
 
 }  // extern "C"

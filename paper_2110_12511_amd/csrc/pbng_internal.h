@@ -70,6 +70,10 @@ struct Ctx {
     size_t ev_next = 0;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> intervals[PBNG_K_NCLASS];
     KCounters *kctr = nullptr;  // device [PBNG_K_NCLASS], zeroed per call
+    // learned range-bound predictor: parameters, Adam moments, gradient sums
+    float *mlp_p = nullptr, *mlp_m = nullptr, *mlp_v = nullptr, *mlp_g = nullptr, *mlp_acc = nullptr;
+    int mlp_t = 0;
+    bool mlp_ready = false;
     template <class T>
     T *alloc(size_t n) {
         return static_cast<T *>(arena.take((n ? n : 1) * sizeof(T)));
@@ -165,6 +169,17 @@ u64 count_pass_xside(Ctx &c, const DevGraph &G, u64 *sup_label, const unsigned c
 // when the options allow it (mfma.hip), everything else by traversal.
 // Returns the wedges walked.
 u64 count_side(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 *out);
+
+// learned range bounds (learned.hip)
+void mlp_init(Ctx &c, u64 seed);
+void mlp_set(Ctx &c, const float *host);
+void mlp_get(Ctx &c, float *host);
+void mlp_forward(Ctx &c, const float *X, i64 n, float *out);
+void mlp_loss_grad(Ctx &c, const float *X, const float *Y, const float *Wt, i64 n, float *grad, float *loss_host);
+void mlp_train(Ctx &c, const float *X, const float *Y, const float *Wt, i64 n, int batch, int epochs, float lr,
+               float *epoch_loss);
+void tip_features(Ctx &c, const DevGraph &G, int side, const u64 *sup, float *F);
+void learned_theta_hat(Ctx &c, const DevGraph &G, int side, const u64 *sup, u64 *theta_hat);
 
 int bits_for(u64 maxval);
 int grid_1d(i64 n, int block = 256, int cap = 16384);

@@ -1085,6 +1085,11 @@ __global__ void k_compact(const i32 *dirty, const u32 *ndirty, const i64 *yrow, 
     }
 }
 
+// the learned bound never falls to or below the smallest alive support
+__global__ void k_learned_guard(TipCtl *ctl, const u64 *mn) {
+    if (ctl->s < mn[0]) ctl->s = mn[0];
+}
+
 __global__ void k_set_bound(TipCtl *ctl, int last) {
     ctl->bound = last ? ~0ull : ctl->s + 1;
     ctl->nF = 0;
@@ -1502,6 +1507,18 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
     unsigned char *alive_label = c.alloc<unsigned char>(G.n);
     u64 *sup_label = c.alloc<u64>(G.n);
     u64 *rmin = c.alloc<u64>(2);
+    // learned rule: predicted tip numbers from the initial graph
+    u64 *that = nullptr;
+    double *one_dev = nullptr;
+    c.stats.bound_rule_used = o.bound_rule == PBNG_BOUND_RANDOM ? PBNG_BOUND_RANDOM : PBNG_BOUND_PLAIN;
+    if (o.bound_rule == PBNG_BOUND_LEARNED && c.mlp_ready) {
+        that = c.alloc<u64>(nx);
+        learned_theta_hat(c, G, side, sup, that);
+        one_dev = c.alloc<double>(1);
+        const double one = 1.0;
+        PBNG_HIP(hipMemcpyAsync(one_dev, &one, sizeof(double), hipMemcpyHostToDevice, s));
+        c.stats.bound_rule_used = PBNG_BOUND_LEARNED;
+    }
     // LDS key tiles for heavy active vertices (one 512-lane workgroup per CU)
     const i32 ntiles = (i32)((nx + (i64(1) << TILE_LOG) - 1) >> TILE_LOG);
     const int tslots = c.num_cu;
@@ -1602,6 +1619,16 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
                                    rmin, rmin + 1);
                 hipLaunchKernelGGL(k_random_pick, dim3(1), dim3(1), 0, s, ctl, (const u64 *)rmin, (const u64 *)(rmin + 1),
                                    (u64)o.seed, pid);
+                PBNG_LAUNCH_CHECK();
+            } else if (that) {
+                // work-weighted quantile of the predicted tip numbers, kept
+                // above the smallest alive support so the partition is never empty
+                weighted_select(c, that, w, st, ST_ALIVE, nx, nullptr, one_dev, P - pid, &ctl->s, &ctl->est_init);
+                u64 init2[2] = {~0ull, 0};
+                PBNG_HIP(hipMemcpyAsync(rmin, init2, sizeof(init2), hipMemcpyHostToDevice, s));
+                hipLaunchKernelGGL(k_random_bound, dim3(gx), dim3(256), 0, s, (const u64 *)sup, (const unsigned char *)st, nx,
+                                   rmin, rmin + 1);
+                hipLaunchKernelGGL(k_learned_guard, dim3(1), dim3(1), 0, s, ctl, (const u64 *)rmin);
                 PBNG_LAUNCH_CHECK();
             } else {
                 weighted_select(c, sup, w, st, ST_ALIVE, nx, nullptr, &ctl->scale, P - pid, &ctl->s, &ctl->est_init);

@@ -27,7 +27,7 @@ def test_struct_layouts():
     # pbng_csr: 3 x int64 + 2 pointers + int32 (+pad); pbng_opts: 8 x int32
     assert ctypes.sizeof(binding.Csr) == 48
     assert ctypes.sizeof(binding.Opts) == 32
-    assert ctypes.sizeof(binding.Stats) == 6 * 8 + 10 * 8 + 2 * 4 + 3 * 8 + binding.K_NCLASS * 32
+    assert ctypes.sizeof(binding.Stats) == 6 * 8 + 10 * 8 + 4 * 4 + 3 * 8 + binding.K_NCLASS * 32
 
 
 def test_null_context_rejected():
