@@ -85,8 +85,13 @@ typedef enum {
                                    instead of bloom-aggregated batches
                                    (Section 5.1)                            */
 #define PBNG_F_NO_DENSE_TILE 0x4 /* counting: scalar path for hub pairs too */
-#define PBNG_F_KERNEL_TIMING 0x8 /* time kernel classes with HIP events on the
-                                    context stream (fills pbng_stats.kstat) */
+#define PBNG_F_KERNEL_TIMING 0x8 /* time kernel classes with HIP events on
+                                    the context stream (fills
+                                    pbng_stats.kstat)                       */
+#define PBNG_F_HOST_ROUNDS 0x10  /* wing: coarse-grained rounds driven from
+                                    the host, one synchronisation per round,
+                                    instead of replays of a captured HIP
+                                    graph of several rounds                  */
 
 /* Kernel classes timed under PBNG_F_KERNEL_TIMING. */
 enum {
@@ -119,7 +124,9 @@ typedef struct {
                            more live wedges than this count in LDS key tiles,
                            others in LDS hash ranges; 0 = library default
                            (2^18), negative = never (schedule only)          */
-    int32_t reserved[2];
+    int32_t batch_edges;/* batch calls: most edges packed into one union
+                           graph; 0 = library default (2^28)                 */
+    int32_t reserved;
 } pbng_opts;
 
 /* Per-call counters and phase times of the last compute call. */
@@ -164,6 +171,26 @@ int pbng_tip(pbng_ctx *ctx, const pbng_csr *g, pbng_side side,
  * wing_out: uint64[m].  opts may be NULL.                                 */
 int pbng_wing(pbng_ctx *ctx, const pbng_csr *g, const pbng_opts *opts,
               uint64_t *wing_out);
+
+/* ---- Many graphs per call ------------------------------------------------
+ *
+ * Tip numbers of one side / wing numbers of every edge of ng graphs.  A
+ * butterfly never spans two connected components, so the graphs are packed
+ * into their disjoint union (ids shifted by the totals of the graphs before)
+ * and decomposed together: every launch, every coarse-grained round and the
+ * one persistent fine-grained launch serve all graphs of a chunk, and its
+ * fine-grained queue holds partitions of every graph.  Chunks are runs of
+ * consecutive graphs with at most opts->batch_edges edges (a larger graph
+ * forms a chunk of its own).  Results equal the single-graph calls'.
+ *
+ * g: host array of ng descriptors, all with the same on_device; outs: host
+ * array of ng output pointers in that memory space, outs[k] of n_u[k] / n_v[k]
+ * (tip) or m[k] (wing) entries.  Statistics sum over chunks.                */
+int pbng_tip_batch(pbng_ctx *ctx, const pbng_csr *g, int32_t ng,
+                   pbng_side side, const pbng_opts *opts,
+                   uint64_t *const *outs);
+int pbng_wing_batch(pbng_ctx *ctx, const pbng_csr *g, int32_t ng,
+                    const pbng_opts *opts, uint64_t *const *outs);
 
 /* ---- Learned range bounds (Section 3.1.3 replaced by a predictor) -------
  *

@@ -16,6 +16,7 @@ from .binding import (  # noqa: F401
     F_NO_BATCH,
     F_NO_DENSE_TILE,
     F_NO_DYNAMIC,
+    F_HOST_ROUNDS,
     Context,
     DeviceGraph,
     PbngError,
@@ -23,7 +24,9 @@ from .binding import (  # noqa: F401
     host_csr,
     make_opts,
     tip,
+    tip_batch,
     tip_features,
+    wing_batch,
     to_numpy_u64,
     wing,
     load,

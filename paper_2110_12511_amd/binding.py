@@ -55,13 +55,15 @@ class Opts(ctypes.Structure):
         ("seed", ctypes.c_int32),
         ("dense_cut", ctypes.c_int32),
         ("tile_w", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 2),
+        ("batch_edges", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
 K_COUNT, K_TIP_PEEL, K_FD, K_WING_CD, K_DENSE, K_NCLASS = 0, 1, 2, 3, 4, 5
 K_NAMES = ["count", "tip_peel", "fd", "wing_cd", "dense"]
 F_KERNEL_TIMING = 0x8
+F_HOST_ROUNDS = 0x10
 
 
 class KernelStat(ctypes.Structure):
@@ -113,7 +115,7 @@ class Stats(ctypes.Structure):
 
 EXPORTS = ["pbng_create", "pbng_destroy", "pbng_last_error", "pbng_last_stats", "pbng_count", "pbng_tip", "pbng_wing",
            "pbng_tip_features", "pbng_mlp_init", "pbng_mlp_set", "pbng_mlp_get", "pbng_mlp_forward",
-           "pbng_mlp_loss_grad", "pbng_mlp_train"]
+           "pbng_mlp_loss_grad", "pbng_mlp_train", "pbng_tip_batch", "pbng_wing_batch"]
 MLP_NPARAM = 8961
 
 _lib = None
@@ -156,6 +158,8 @@ def load():
         "pbng_mlp_forward": [vp, vp, i64, vp],
         "pbng_mlp_loss_grad": [vp, vp, vp, vp, i64, vp, vp],
         "pbng_mlp_train": [vp, vp, vp, vp, i64, ctypes.c_int32, ctypes.c_int32, f32, vp],
+        "pbng_tip_batch": [vp, vp, ctypes.c_int32, ctypes.c_int, ctypes.POINTER(Opts), vp],
+        "pbng_wing_batch": [vp, vp, ctypes.c_int32, ctypes.POINTER(Opts), vp],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -165,10 +169,10 @@ def load():
     return lib
 
 
-def make_opts(P=0, bound_rule=BOUND_PLAIN, flags=0, seed=0, dense_cut=0, tile_w=0) -> Opts:
+def make_opts(P=0, bound_rule=BOUND_PLAIN, flags=0, seed=0, dense_cut=0, tile_w=0, batch_edges=0) -> Opts:
     o = Opts()
     o.P, o.bound_rule, o.flags, o.seed, o.dense_cut = int(P), int(bound_rule), int(flags), int(seed), int(dense_cut)
-    o.tile_w = int(tile_w)
+    o.tile_w, o.batch_edges = int(tile_w), int(batch_edges)
     return o
 
 
@@ -310,6 +314,35 @@ def tip(ctx: Context, dg: DeviceGraph, side: int, opts: Opts | None = None):
     out = _out_tensor(n)
     ctx.tip_raw(dg.csr(), side, out.data_ptr(), opts)
     return out[:n]
+
+
+def _batch(ctx: Context, graphs, kind: int, side: int, opts: Opts | None):
+    ng = len(graphs)
+    descs = (Csr * max(ng, 1))()
+    outs = []
+    for k, dg in enumerate(graphs):
+        descs[k] = dg.csr()
+        n = dg.m if kind == 1 else (dg.n_u if side == SIDE_U else dg.n_v)
+        outs.append(_out_tensor(n))
+    ptrs = (ctypes.c_void_p * max(ng, 1))(*[t.data_ptr() for t in outs])
+    o = ctypes.byref(opts) if opts else None
+    if kind == 1:
+        rc = ctx.lib.pbng_wing_batch(ctx.h, ctypes.cast(descs, ctypes.c_void_p), ng, o, ctypes.cast(ptrs, ctypes.c_void_p))
+    else:
+        rc = ctx.lib.pbng_tip_batch(ctx.h, ctypes.cast(descs, ctypes.c_void_p), ng, side, o,
+                                    ctypes.cast(ptrs, ctypes.c_void_p))
+    ctx._check(rc)
+    return [t[: (dg.m if kind == 1 else (dg.n_u if side == SIDE_U else dg.n_v))] for t, dg in zip(outs, graphs)]
+
+
+def tip_batch(ctx: Context, graphs, side: int, opts: Opts | None = None):
+    """Tip numbers of one side of every DeviceGraph in `graphs` (one call)."""
+    return _batch(ctx, graphs, 0, side, opts)
+
+
+def wing_batch(ctx: Context, graphs, opts: Opts | None = None):
+    """Wing numbers of every edge of every DeviceGraph in `graphs` (one call)."""
+    return _batch(ctx, graphs, 1, 0, opts)
 
 
 def tip_features(ctx: Context, dg: DeviceGraph, side: int):

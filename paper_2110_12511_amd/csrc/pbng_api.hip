@@ -1,6 +1,8 @@
 // C ABI of the library (include/pbng.h): argument checks, host/device
 // marshalling of the caller's graph, phase timing, error translation.
+#include <algorithm>
 #include <chrono>
+#include <string>
 #include <cstring>
 
 #include "pbng_internal.h"
@@ -140,6 +142,7 @@ void pbng_destroy(pbng_ctx *x) {
     if (x->c.sel_scratch) (void)hipFree(x->c.sel_scratch);
     if (x->c.kctr) (void)hipFree(x->c.kctr);
     if (x->c.mlp_p) (void)hipFree(x->c.mlp_p);
+    if (x->c.cap_stream) (void)hipStreamDestroy(x->c.cap_stream);
     for (hipEvent_t e : x->c.ev_pool) (void)hipEventDestroy(e);
     delete x;
 }
@@ -237,6 +240,87 @@ int pbng_wing(pbng_ctx *x, const pbng_csr *g, const pbng_opts *opts, uint64_t *w
         if (o.flags & PBNG_F_KERNEL_TIMING) c.timing_end_call();
         c.stats.ms_total = ms_since(t0);
     });
+}
+
+}  // extern "C"
+
+namespace pbng {
+namespace {
+
+void add_stats(pbng_stats &a, const pbng_stats &b) {
+    a.ms_prep += b.ms_prep;
+    a.ms_count += b.ms_count;
+    a.ms_cd += b.ms_cd;
+    a.ms_fd_prep += b.ms_fd_prep;
+    a.ms_fd += b.ms_fd;
+    a.wedges += b.wedges;
+    a.wedges_count += b.wedges_count;
+    a.wedges_cd += b.wedges_cd;
+    a.wedges_fd += b.wedges_fd;
+    a.updates += b.updates;
+    a.links += b.links;
+    a.blooms += b.blooms;
+    a.bloom_pairs += b.bloom_pairs;
+    a.rho += b.rho;
+    a.recounts += b.recounts;
+    a.partitions += b.partitions;
+    a.P_used = b.P_used;
+    a.bound_rule_used = b.bound_rule_used;
+    a.fd_work_max = std::max(a.fd_work_max, b.fd_work_max);
+    a.fd_work_sum += b.fd_work_sum;
+    a.dense_pairs += b.dense_pairs;
+}
+
+int batch_call(pbng_ctx *x, const pbng_csr *g, int32_t ng, int kind, int side, const pbng_opts *opts,
+               uint64_t *const *outs) {
+    if (!x) return PBNG_E_ARG;
+    Ctx &c = x->c;
+    if (ng < 0 || (ng > 0 && (!g || !outs))) return fail(c, PBNG_E_ARG, "bad batch arguments");
+    for (int k = 0; k < ng; ++k) {
+        const int rc = check_csr(&g[k]);
+        if (rc) return fail(c, rc, "bad graph arguments in batch entry " + std::to_string(k));
+        if ((g[k].on_device != 0) != (g[0].on_device != 0))
+            return fail(c, PBNG_E_ARG, "batch mixes host and device graphs");
+        const i64 n = kind == 1 ? g[k].m : (side == 0 ? g[k].n_u : g[k].n_v);
+        if (n > 0 && !outs[k]) return fail(c, PBNG_E_ARG, "null output in batch entry " + std::to_string(k));
+    }
+    CallScope scope(c);
+    pbng_opts o = default_opts(opts);
+    const i64 max_m = o.batch_edges > 0 ? (i64)o.batch_edges : (i64(1) << 28);
+    return guarded(c, [&] {
+        auto t0 = std::chrono::steady_clock::now();
+        c.timing_begin_call((o.flags & PBNG_F_KERNEL_TIMING) != 0);
+        pbng_stats acc{};
+        for (int first = 0; first < ng;) {
+            const int last = (int)batch_chunk_end(g, ng, first, max_m);
+            c.stats = pbng_stats{};
+            batch_run(c, g, first, last, kind, side, o, outs);
+            add_stats(acc, c.stats);
+            c.arena.release_all();
+            first = last;
+        }
+        c.stats = acc;
+        if (o.flags & PBNG_F_KERNEL_TIMING) c.timing_end_call();
+        c.stats.ms_total = ms_since(t0);
+    });
+}
+
+}  // namespace
+}  // namespace pbng
+
+extern "C" {
+
+int pbng_tip_batch(pbng_ctx *x, const pbng_csr *g, int32_t ng, pbng_side side, const pbng_opts *opts,
+                   uint64_t *const *outs) {
+    if (side != PBNG_SIDE_U && side != PBNG_SIDE_V) {
+        if (x) x->c.last_error = "bad side";
+        return PBNG_E_ARG;
+    }
+    return batch_call(x, g, ng, 0, side, opts, outs);
+}
+
+int pbng_wing_batch(pbng_ctx *x, const pbng_csr *g, int32_t ng, const pbng_opts *opts, uint64_t *const *outs) {
+    return batch_call(x, g, ng, 1, 0, opts, outs);
 }
 
 int pbng_tip_features(pbng_ctx *x, const pbng_csr *g, pbng_side side, float *feat) {

@@ -74,6 +74,9 @@ struct Ctx {
     float *mlp_p = nullptr, *mlp_m = nullptr, *mlp_v = nullptr, *mlp_g = nullptr, *mlp_acc = nullptr;
     int mlp_t = 0;
     bool mlp_ready = false;
+    // stream used only to capture round graphs (replayed on `stream`)
+    hipStream_t cap_stream = nullptr;
+    hipStream_t capture_stream();
     template <class T>
     T *alloc(size_t n) {
         return static_cast<T *>(arena.take((n ? n : 1) * sizeof(T)));
@@ -169,6 +172,22 @@ u64 count_pass_xside(Ctx &c, const DevGraph &G, u64 *sup_label, const unsigned c
 // when the options allow it (mfma.hip), everything else by traversal.
 // Returns the wedges walked.
 u64 count_side(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 *out);
+
+// owner of an instantiated HIP graph
+struct GraphExec {
+    hipGraphExec_t e = nullptr;
+    GraphExec() = default;
+    GraphExec(const GraphExec &) = delete;
+    GraphExec &operator=(const GraphExec &) = delete;
+    ~GraphExec() {
+        if (e) (void)hipGraphExecDestroy(e);
+    }
+};
+
+// many graphs per call (batch.hip)
+i64 batch_chunk_end(const pbng_csr *g, int ng, int first, i64 max_m);
+void batch_run(Ctx &c, const pbng_csr *g, int first, int last, int kind, int side, const pbng_opts &o,
+               uint64_t *const *outs);
 
 // learned range bounds (learned.hip)
 void mlp_init(Ctx &c, u64 seed);

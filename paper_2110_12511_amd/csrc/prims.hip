@@ -60,6 +60,12 @@ hipEvent_t Ctx::event() {
     return ev_pool[ev_next++];
 }
 
+hipStream_t Ctx::capture_stream() {
+    // non-blocking, default priority
+    if (!cap_stream) PBNG_HIP(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
+    return cap_stream;
+}
+
 void Ctx::kbegin(int cls) {
     if (!timing) return;
     hipEvent_t a = event(), b = event();

@@ -51,7 +51,15 @@ struct WingCtl {
     u32 pad;
     u64 updates;    // support updates
     u64 links;      // links walked
+    i32 pid;        // partition being built
+    u32 pad2;
+    u64 rounds;     // rounds that had active edges
+    i64 alive;      // edges neither peeled nor active
 };
+
+// rounds per replay of the captured coarse-grained round graph (even, so the
+// two active-set buffers are back in place after a replay)
+constexpr int W_GRAPH_K = 4;
 
 // ------------------------------------------------------------------ CD kernels
 
@@ -192,8 +200,9 @@ __global__ void w_retire(const i32 *F, const u32 *nF, unsigned char *st, const u
     if ((threadIdx.x & 63) == 0 && s) atomicAdd((unsigned long long *)&ctl->est_final, (unsigned long long)s);
 }
 
-__global__ void w_activate(const i32 *F2, const u32 *nF2, unsigned char *st, i32 *part, i32 pid) {
+__global__ void w_activate(const i32 *F2, const u32 *nF2, unsigned char *st, i32 *part, const WingCtl *ctl) {
     const u32 n = *nF2;
+    const i32 pid = ctl->pid;
     for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) {
         const i32 e = F2[i];
         st[e] = WS_ACTIVE;
@@ -201,19 +210,28 @@ __global__ void w_activate(const i32 *F2, const u32 *nF2, unsigned char *st, i32
     }
 }
 
-__global__ void w_set_bound(WingCtl *ctl, int last) {
+__global__ void w_set_bound(WingCtl *ctl, int last, i32 pid) {
     ctl->bound = last ? ~0ull : ctl->s + 1;
     ctl->nF = 0;
     ctl->nF2 = 0;
     ctl->ntouch = 0;
     ctl->est_final = 0;
+    ctl->pid = pid;
 }
 
+// the next active set becomes current; the retired edges leave the alive count
 __global__ void w_next_round(WingCtl *ctl) {
+    if (ctl->nF) {
+        ctl->rounds += 1;
+        ctl->alive -= (i64)ctl->nF;
+    }
     ctl->nF = ctl->nF2;
     ctl->nF2 = 0;
     ctl->ntouch = 0;
 }
+
+// alive count after a partition's first active set is drawn
+__global__ void w_alive_init(WingCtl *ctl, i64 m) { ctl->alive = m; }
 
 __global__ void w_scale(WingCtl *ctl) {
     const double fin = (double)ctl->est_final;
@@ -684,6 +702,45 @@ void wing_decompose(Ctx &c, const DevGraph &G, const pbng_opts &o, u64 *theta) {
     const int gm = grid_1d(m);
 
     // ---- coarse-grained phase
+    // Rounds are either driven from the host (one synchronisation per round
+    // to read the active-set size) or captured once into a HIP graph of
+    // W_GRAPH_K rounds with fixed grids that is replayed until the active set
+    // is empty (one synchronisation per replay).  Rounds past the end of a
+    // partition find an empty active set and do nothing.
+    const bool host_rounds = (o.flags & PBNG_F_HOST_ROUNDS) != 0;
+    const int gfix = c.num_cu * 8;
+    auto round_fixed = [&](hipStream_t rs, i32 *Fa, i32 *Fb) {
+        hipLaunchKernelGGL(w_links, dim3(gfix), dim3(256), 0, rs, (const i32 *)Fa, (const u32 *)&ctl->nF, (const i64 *)I.eoff,
+                           (const i32 *)I.ebloom, (const i32 *)I.etwin, (const unsigned char *)st, (const u32 *)bk, bcount,
+                           touched, sup, ctl, Fb, c.kctr + PBNG_K_WING_CD);
+        hipLaunchKernelGGL(w_blooms, dim3(gfix), dim3(256), 0, rs, (const i32 *)touched, (const u32 *)&ctl->ntouch,
+                           (const i64 *)I.boff, blen, bk, bcount, cedge, (const unsigned char *)st, sup, ctl, Fb,
+                           dynamic ? 1 : 0, c.kctr + PBNG_K_WING_CD);
+        hipLaunchKernelGGL(w_retire, dim3(c.num_cu * 2), dim3(256), 0, rs, (const i32 *)Fa, (const u32 *)&ctl->nF, st,
+                           (const u64 *)init, ctl);
+        hipLaunchKernelGGL(w_activate, dim3(c.num_cu * 2), dim3(256), 0, rs, (const i32 *)Fb, (const u32 *)&ctl->nF2, st,
+                           part, (const WingCtl *)ctl);
+        hipLaunchKernelGGL(w_next_round, dim3(1), dim3(1), 0, rs, ctl);
+    };
+    GraphExec rounds_exec;
+    if (!host_rounds) {
+        hipStream_t cs = c.capture_stream();
+        PBNG_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        i32 *Fa = F, *Fb = F2;
+        for (int r = 0; r < W_GRAPH_K; ++r) {
+            round_fixed(cs, Fa, Fb);
+            std::swap(Fa, Fb);
+        }
+        const hipError_t le = hipGetLastError();
+        hipGraph_t graph = nullptr;
+        const hipError_t ee = hipStreamEndCapture(cs, &graph);
+        PBNG_HIP(le);
+        PBNG_HIP(ee);
+        const hipError_t ie = hipGraphInstantiate(&rounds_exec.e, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        PBNG_HIP(ie);
+    }
+    hipLaunchKernelGGL(w_alive_init, dim3(1), dim3(1), 0, s, ctl, m);
     i64 n_alive = m;
     int pid = 0;
     u64 rho = 0;
@@ -703,43 +760,68 @@ void wing_decompose(Ctx &c, const DevGraph &G, const pbng_opts &o, u64 *theta) {
                 weighted_select(c, sup, sup, st, WS_ALIVE, m, nullptr, &ctl->scale, P - pid, &ctl->s, &ctl->est_init);
             }
         }
-        hipLaunchKernelGGL(w_set_bound, dim3(1), dim3(1), 0, s, ctl, last ? 1 : 0);
+        hipLaunchKernelGGL(w_set_bound, dim3(1), dim3(1), 0, s, ctl, last ? 1 : 0, (i32)pid);
         hipLaunchKernelGGL(w_frontier, dim3(gm), dim3(256), 0, s, st, (const u64 *)sup, init, part, m, ctl, pid, F);
         PBNG_LAUNCH_CHECK();
-        u32 nF = read_scalar<u32>(c, &ctl->nF);
-        while (nF > 0) {
-            ++rho;
-            const int gw = grid_1d((i64)nF * WAVE);
-            if ((i64)nF == n_alive) {
+        if (!host_rounds) {
+            for (;;) {
+                WingCtl h;
+                PBNG_HIP(hipMemcpyAsync(&h, ctl, sizeof(WingCtl), hipMemcpyDeviceToHost, s));
+                PBNG_HIP(hipStreamSynchronize(s));
+                n_alive = h.alive;
+                if (h.nF == 0) break;
+                if ((i64)h.nF == h.alive) {
+                    // everything left is active: retire it without updates
+                    hipLaunchKernelGGL(w_retire, dim3(grid_1d(h.nF)), dim3(256), 0, s, (const i32 *)F,
+                                       (const u32 *)&ctl->nF, st, (const u64 *)init, ctl);
+                    PBNG_LAUNCH_CHECK();
+                    ++rho;
+                    n_alive = 0;
+                    break;
+                }
+                c.kbegin(PBNG_K_WING_CD);
+                PBNG_HIP(hipGraphLaunch(rounds_exec.e, s));
+                c.kend(PBNG_K_WING_CD);
+            }
+        } else {
+            u32 nF = read_scalar<u32>(c, &ctl->nF);
+            while (nF > 0) {
+                ++rho;
+                const int gw = grid_1d((i64)nF * WAVE);
+                if ((i64)nF == n_alive) {
+                    hipLaunchKernelGGL(w_retire, dim3(grid_1d(nF)), dim3(256), 0, s, (const i32 *)F, (const u32 *)&ctl->nF, st,
+                                       (const u64 *)init, ctl);
+                    PBNG_LAUNCH_CHECK();
+                    n_alive = 0;
+                    break;
+                }
+                c.kbegin(PBNG_K_WING_CD);
+                hipLaunchKernelGGL(w_links, dim3(gw), dim3(256), 0, s, (const i32 *)F, (const u32 *)&ctl->nF,
+                                   (const i64 *)I.eoff, (const i32 *)I.ebloom, (const i32 *)I.etwin, (const unsigned char *)st,
+                                   (const u32 *)bk, bcount, touched, sup, ctl, F2, c.kctr + PBNG_K_WING_CD);
+                PBNG_LAUNCH_CHECK();
+                hipLaunchKernelGGL(w_blooms, dim3(grid_1d((i64)std::min<i64>(nbl, (i64)nF * 64) * WAVE)), dim3(256), 0, s,
+                                   (const i32 *)touched, (const u32 *)&ctl->ntouch, (const i64 *)I.boff, blen, bk, bcount,
+                                   cedge, (const unsigned char *)st, sup, ctl, F2, dynamic ? 1 : 0,
+                                   c.kctr + PBNG_K_WING_CD);
+                c.kend(PBNG_K_WING_CD);
+                PBNG_LAUNCH_CHECK();
                 hipLaunchKernelGGL(w_retire, dim3(grid_1d(nF)), dim3(256), 0, s, (const i32 *)F, (const u32 *)&ctl->nF, st,
                                    (const u64 *)init, ctl);
+                hipLaunchKernelGGL(w_activate, dim3(gm), dim3(256), 0, s, (const i32 *)F2, (const u32 *)&ctl->nF2, st, part,
+                                   (const WingCtl *)ctl);
+                hipLaunchKernelGGL(w_next_round, dim3(1), dim3(1), 0, s, ctl);
                 PBNG_LAUNCH_CHECK();
-                n_alive = 0;
-                break;
+                n_alive -= nF;
+                std::swap(F, F2);
+                nF = read_scalar<u32>(c, &ctl->nF);
             }
-            c.kbegin(PBNG_K_WING_CD);
-            hipLaunchKernelGGL(w_links, dim3(gw), dim3(256), 0, s, (const i32 *)F, (const u32 *)&ctl->nF, (const i64 *)I.eoff,
-                               (const i32 *)I.ebloom, (const i32 *)I.etwin, (const unsigned char *)st, (const u32 *)bk,
-                               bcount, touched, sup, ctl, F2, c.kctr + PBNG_K_WING_CD);
-            PBNG_LAUNCH_CHECK();
-            hipLaunchKernelGGL(w_blooms, dim3(grid_1d((i64)std::min<i64>(nbl, (i64)nF * 64) * WAVE)), dim3(256), 0, s,
-                               (const i32 *)touched, (const u32 *)&ctl->ntouch, (const i64 *)I.boff, blen, bk, bcount, cedge,
-                               (const unsigned char *)st, sup, ctl, F2, dynamic ? 1 : 0, c.kctr + PBNG_K_WING_CD);
-            c.kend(PBNG_K_WING_CD);
-            PBNG_LAUNCH_CHECK();
-            hipLaunchKernelGGL(w_retire, dim3(grid_1d(nF)), dim3(256), 0, s, (const i32 *)F, (const u32 *)&ctl->nF, st,
-                               (const u64 *)init, ctl);
-            hipLaunchKernelGGL(w_activate, dim3(gm), dim3(256), 0, s, (const i32 *)F2, (const u32 *)&ctl->nF2, st, part, pid);
-            hipLaunchKernelGGL(w_next_round, dim3(1), dim3(1), 0, s, ctl);
-            PBNG_LAUNCH_CHECK();
-            n_alive -= nF;
-            std::swap(F, F2);
-            nF = read_scalar<u32>(c, &ctl->nF);
         }
         hipLaunchKernelGGL(w_scale, dim3(1), dim3(1), 0, s, ctl);
         PBNG_LAUNCH_CHECK();
         ++pid;
     }
+    if (!host_rounds) rho += read_scalar<u64>(c, &ctl->rounds);
     const i32 np = pid;
     c.stats.rho = rho;
     c.stats.partitions = np;

@@ -1,0 +1,97 @@
+"""Many graphs per call: the batched tip and wing entry points return exactly
+the per-graph results (oracle on small graphs, single-graph calls on the
+rest), for device and host buffers and across chunk boundaries."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2110_12511_amd as pb
+from paper_2110_12511_amd import binding
+import synth
+from gpu_util import u64
+
+pytestmark = pytest.mark.gpu
+
+
+def small_graphs(n, seed):
+    rng = np.random.default_rng(seed)
+    gs = [synth.complete(3, 4), synth.from_edges(3, 2, []), synth.from_edges(1, 1, [(0, 0)])]
+    while len(gs) < n:
+        gs.append(synth.random_small(int(rng.integers(1, 13)), int(rng.integers(1, 10)),
+                                     float(rng.choice([0.3, 0.6, 0.9])), seed=int(rng.integers(1 << 30))))
+    gs.append(synth.er(300, 200, 2500, seed=5))
+    gs.append(synth.chung_lu(800, 300, 4000, 2.2, 200, seed=6))
+    return gs
+
+
+@pytest.mark.parametrize("side", [0, 1])
+@pytest.mark.parametrize("batch_edges", [0, 40, 3000])
+def test_tip_batch_matches_oracle(ctx, side, batch_edges):
+    gs = small_graphs(40, 1)
+    res = pb.tip_batch(ctx, [pb.DeviceGraph.from_graph(g) for g in gs], side, pb.make_opts(P=6, batch_edges=batch_edges))
+    for g, r in zip(gs, res):
+        assert np.array_equal(u64(r), oracle.tip(g, side)), g.name
+
+
+@pytest.mark.parametrize("batch_edges", [0, 60])
+def test_wing_batch_matches_oracle(ctx, batch_edges):
+    gs = small_graphs(30, 2)
+    res = pb.wing_batch(ctx, [pb.DeviceGraph.from_graph(g) for g in gs], pb.make_opts(P=5, batch_edges=batch_edges))
+    for g, r in zip(gs, res):
+        assert np.array_equal(u64(r), oracle.wing(g)), g.name
+
+
+def test_batch_host_buffers(ctx):
+    gs = small_graphs(12, 3)
+    descs = (binding.Csr * len(gs))()
+    keep, outs = [], []
+    for k, g in enumerate(gs):
+        rp = np.ascontiguousarray(g.row_ptr, np.int64)
+        ci = np.ascontiguousarray(g.col_idx, np.int32)
+        keep += [rp, ci]
+        descs[k] = pb.host_csr(g.n_u, g.n_v, rp, ci)
+        outs.append(np.zeros(max(g.n_v, 1), np.uint64))
+    ptrs = (ctypes.c_void_p * len(gs))(*[o.ctypes.data for o in outs])
+    rc = ctx.lib.pbng_tip_batch(ctx.h, ctypes.cast(descs, ctypes.c_void_p), len(gs), pb.SIDE_V,
+                                ctypes.byref(pb.make_opts(P=4, batch_edges=100)), ctypes.cast(ptrs, ctypes.c_void_p))
+    assert rc == 0
+    for g, o in zip(gs, outs):
+        assert np.array_equal(o[: g.n_v], oracle.tip(g, 1))
+
+
+def test_batch_rejects_bad_entry(ctx):
+    bad = synth.from_edges(2, 2, [(0, 1), (0, 0)])  # unsorted row
+    good = synth.complete(2, 2)
+    gs = [pb.DeviceGraph.from_graph(good), pb.DeviceGraph(bad.n_u, bad.n_v, bad.row_ptr, np.array([1, 0], np.int32))]
+    with pytest.raises(pb.PbngError) as e:
+        pb.tip_batch(ctx, gs, 0)
+    assert e.value.code == -2
+
+
+def mixed_graph(gi):
+    """Graph gi of a family of uneven sizes: m log-uniform in [1e3, 1e5]; even
+    gi Erdos-Renyi (|U| = m/10, |V| = m/20), odd gi Chung-Lu (exponent in
+    [2.0, 2.6], |U| = m/10, |V| = m/50, cap 50000)."""
+    rng = np.random.default_rng(50000 + gi)
+    m = int(round(np.exp(rng.uniform(np.log(1e3), np.log(1e5)))))
+    if gi % 2 == 0:
+        return synth.er(max(m // 10, 2), max(m // 20, 2), m, seed=50000 + gi)
+    return synth.chung_lu(max(m // 10, 2), max(m // 50, 2), m, float(rng.uniform(2.0, 2.6)), 50000, seed=50000 + gi)
+
+
+def test_uneven_batch_matches_single_calls(ctx):
+    gs = [mixed_graph(i) for i in range(96)]
+    dgs = [pb.DeviceGraph.from_graph(g) for g in gs]
+    res = pb.tip_batch(ctx, dgs, 0)
+    st = ctx.stats()
+    assert st["partitions"] >= 1
+    for k, (dg, r) in enumerate(zip(dgs, res)):
+        assert np.array_equal(u64(r), u64(pb.tip(ctx, dg, 0))), k
+    for k in range(0, 96, 12):
+        assert np.array_equal(u64(res[k]), oracle.tip(gs[k], 0)), k
+    small = [k for k, g in enumerate(gs) if g.m <= 4000]
+    wres = pb.wing_batch(ctx, [dgs[k] for k in small])
+    for k, r in zip(small, wres):
+        assert np.array_equal(u64(r), u64(pb.wing(ctx, dgs[k]))), k

@@ -126,3 +126,29 @@ def test_learned_without_predictor_falls_back(cl_mid):
     assert np.array_equal(u64(pb.tip(c2, dg, 0, pb.make_opts(P=40, bound_rule=pb.BOUND_LEARNED))), eu)
     assert c2.stats()["bound_rule_used"] == pb.BOUND_PLAIN
     c2.close()
+
+
+def test_stored_predictor_gain(ctx):
+    """What the stored network (trained on 2000 seeded graphs) gains: on a
+    held-out graph its predicted ratios theta / support are much closer to
+    the true ones than the best constant ratio, and learned bounds leave every
+    tip number unchanged.  Schedule figures of both rules are printed."""
+    if not predictor.install(ctx):
+        pytest.skip("no stored predictor parameters")
+    g = synth.chung_lu(200000, 40000, 2000000, 2.0, 50000, seed=4)
+    X, R = predictor.rows_for_graph(ctx, g)
+    rhat = ctx.mlp_forward(X)
+    mae_net = float((rhat - R).abs().mean())
+    mae_const = float((R - R.median()).abs().mean())
+    print(f"held-out ratio MAE: network {mae_net:.4f}, best constant {mae_const:.4f}")
+    assert mae_net < 0.5 * mae_const
+    dg = pb.DeviceGraph.from_graph(g)
+    out = {}
+    for name, rule in (("plain", pb.BOUND_PLAIN), ("learned", pb.BOUND_LEARNED)):
+        th = u64(pb.tip(ctx, dg, 0, pb.make_opts(P=150, bound_rule=rule)))
+        st = ctx.stats()
+        out[name] = th
+        imb = st["fd_work_max"] / max(st["fd_work_sum"] / max(st["partitions"], 1), 1)
+        print(f"{name}: {st['ms_total']:.1f} ms, rounds {st['rho']}, partitions {st['partitions']}, "
+              f"fine-grained imbalance {imb:.2f}, rule used {st['bound_rule_used']}")
+    assert np.array_equal(out["plain"], out["learned"])

@@ -84,3 +84,14 @@ def test_wing_full_size_golden(ctx):
     g = synth.config_graph(wl)
     res = gpu_wing(ctx, g, P=400)
     check_golden(rec, res, g.digest())
+
+
+@pytest.mark.parametrize("P", [1, 9, 400])
+def test_wing_host_rounds_match_graph_rounds(ctx, cl_wing, P):
+    """Rounds replayed from a captured HIP graph and rounds driven from the
+    host give the same numbers and the same round count."""
+    g, exp = cl_wing
+    assert np.array_equal(gpu_wing(ctx, g, P=P), exp)
+    rho_graph = ctx.stats()["rho"]
+    assert np.array_equal(gpu_wing(ctx, g, P=P, flags=pb.F_HOST_ROUNDS), exp)
+    assert ctx.stats()["rho"] == rho_graph
