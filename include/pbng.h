@@ -126,7 +126,9 @@ typedef struct {
                            (2^18), negative = never (schedule only)          */
     int32_t batch_edges;/* batch calls: most edges packed into one union
                            graph; 0 = library default (2^28)                 */
-    int32_t reserved;
+    int32_t wide_work;  /* wing: fine-grained work above which a partition
+                           is peeled by device-wide kernels; 0 = library
+                           default (2^24), negative = never (schedule only)  */
 } pbng_opts;
 
 /* Per-call counters and phase times of the last compute call. */
@@ -144,7 +146,8 @@ typedef struct {
     int32_t partitions;       /* partitions actually created                 */
     int32_t P_used;           /* partitions requested after clamping         */
     int32_t bound_rule_used;  /* pbng_bound_rule the call actually used      */
-    int32_t reserved_i;
+    int32_t fd_wide;          /* wing: partitions peeled by device-wide
+                                 kernels instead of one workgroup            */
     uint64_t fd_work_max, fd_work_sum; /* estimated fine-grained work        */
     uint64_t dense_pairs;     /* hub pairs counted on matrix cores           */
     pbng_kernel_stat kstat[PBNG_K_NCLASS];
@@ -191,6 +194,23 @@ int pbng_tip_batch(pbng_ctx *ctx, const pbng_csr *g, int32_t ng,
                    uint64_t *const *outs);
 int pbng_wing_batch(pbng_ctx *ctx, const pbng_csr *g, int32_t ng,
                     const pbng_opts *opts, uint64_t *const *outs);
+
+/* ---- Autotuner -------------------------------------------------------------
+ *
+ * Times one call of `kind` (0: tip numbers of side U, 1: of side V, 2: wing
+ * numbers) on g under schedule settings picked by coordinate descent from
+ * *base (NULL = defaults): first the int8 hub cut-over dense_cut in
+ * {-1 (off), 256, 1024, 4096}, then (tip) the key-tile threshold tile_w in
+ * {2^16, 2^18, 2^20, -1 (never)}, then the partition count P: the base
+ * value against P0/2 and 2 P0 (P0 = base P, else 150 for tip and 400 for
+ * wing).  One untimed warm
+ * run precedes the timed ones; each setting is timed once.  The fastest
+ * setting goes to *best and its time in ms to *ms_best (may be NULL).  The
+ * context caches it under the graph's signature (n_u, n_v, m, largest
+ * degree, kind): a later call for the same signature returns the cached
+ * setting without running anything.  Results never depend on the setting.  */
+int pbng_autotune(pbng_ctx *ctx, const pbng_csr *g, int32_t kind,
+                  const pbng_opts *base, pbng_opts *best, double *ms_best);
 
 /* ---- Learned range bounds (Section 3.1.3 replaced by a predictor) -------
  *

@@ -56,7 +56,7 @@ class Opts(ctypes.Structure):
         ("dense_cut", ctypes.c_int32),
         ("tile_w", ctypes.c_int32),
         ("batch_edges", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("wide_work", ctypes.c_int32),
     ]
 
 
@@ -96,7 +96,7 @@ class Stats(ctypes.Structure):
         ("partitions", ctypes.c_int32),
         ("P_used", ctypes.c_int32),
         ("bound_rule_used", ctypes.c_int32),
-        ("reserved_i", ctypes.c_int32),
+        ("fd_wide", ctypes.c_int32),
         ("fd_work_max", ctypes.c_uint64),
         ("fd_work_sum", ctypes.c_uint64),
         ("dense_pairs", ctypes.c_uint64),
@@ -115,7 +115,7 @@ class Stats(ctypes.Structure):
 
 EXPORTS = ["pbng_create", "pbng_destroy", "pbng_last_error", "pbng_last_stats", "pbng_count", "pbng_tip", "pbng_wing",
            "pbng_tip_features", "pbng_mlp_init", "pbng_mlp_set", "pbng_mlp_get", "pbng_mlp_forward",
-           "pbng_mlp_loss_grad", "pbng_mlp_train", "pbng_tip_batch", "pbng_wing_batch"]
+           "pbng_mlp_loss_grad", "pbng_mlp_train", "pbng_tip_batch", "pbng_wing_batch", "pbng_autotune"]
 MLP_NPARAM = 8961
 
 _lib = None
@@ -160,6 +160,8 @@ def load():
         "pbng_mlp_train": [vp, vp, vp, vp, i64, ctypes.c_int32, ctypes.c_int32, f32, vp],
         "pbng_tip_batch": [vp, vp, ctypes.c_int32, ctypes.c_int, ctypes.POINTER(Opts), vp],
         "pbng_wing_batch": [vp, vp, ctypes.c_int32, ctypes.POINTER(Opts), vp],
+        "pbng_autotune": [vp, ctypes.POINTER(Csr), ctypes.c_int32, ctypes.POINTER(Opts), ctypes.POINTER(Opts),
+                          ctypes.POINTER(ctypes.c_double)],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -169,10 +171,11 @@ def load():
     return lib
 
 
-def make_opts(P=0, bound_rule=BOUND_PLAIN, flags=0, seed=0, dense_cut=0, tile_w=0, batch_edges=0) -> Opts:
+def make_opts(P=0, bound_rule=BOUND_PLAIN, flags=0, seed=0, dense_cut=0, tile_w=0, batch_edges=0,
+              wide_work=0) -> Opts:
     o = Opts()
     o.P, o.bound_rule, o.flags, o.seed, o.dense_cut = int(P), int(bound_rule), int(flags), int(seed), int(dense_cut)
-    o.tile_w, o.batch_edges = int(tile_w), int(batch_edges)
+    o.tile_w, o.batch_edges, o.wide_work = int(tile_w), int(batch_edges), int(wide_work)
     return o
 
 
@@ -218,6 +221,15 @@ class Context:
     def wing_raw(self, csr: Csr, out_ptr: int, opts: Opts | None = None):
         self._check(self.lib.pbng_wing(self.h, ctypes.byref(csr), ctypes.byref(opts) if opts else None,
                                        ctypes.c_void_p(out_ptr)))
+
+    # autotuner ---------------------------------------------------------------
+    def autotune(self, dg, kind: int, base: Opts | None = None):
+        """(best Opts, its time in ms) for kind 0 (tip U), 1 (tip V), 2 (wing)."""
+        best = Opts()
+        ms = ctypes.c_double()
+        self._check(self.lib.pbng_autotune(self.h, ctypes.byref(dg.csr()), int(kind),
+                                           ctypes.byref(base) if base else None, ctypes.byref(best), ctypes.byref(ms)))
+        return best, float(ms.value)
 
     # learned range-bound predictor ----------------------------------------
     def mlp_init(self, seed: int = 0):

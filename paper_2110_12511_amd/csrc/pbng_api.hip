@@ -143,6 +143,7 @@ void pbng_destroy(pbng_ctx *x) {
     if (x->c.kctr) (void)hipFree(x->c.kctr);
     if (x->c.mlp_p) (void)hipFree(x->c.mlp_p);
     if (x->c.cap_stream) (void)hipStreamDestroy(x->c.cap_stream);
+    if (x->c.aux_stream) (void)hipStreamDestroy(x->c.aux_stream);
     for (hipEvent_t e : x->c.ev_pool) (void)hipEventDestroy(e);
     delete x;
 }
@@ -269,6 +270,7 @@ void add_stats(pbng_stats &a, const pbng_stats &b) {
     a.fd_work_max = std::max(a.fd_work_max, b.fd_work_max);
     a.fd_work_sum += b.fd_work_sum;
     a.dense_pairs += b.dense_pairs;
+    a.fd_wide += b.fd_wide;
 }
 
 int batch_call(pbng_ctx *x, const pbng_csr *g, int32_t ng, int kind, int side, const pbng_opts *opts,
@@ -321,6 +323,69 @@ int pbng_tip_batch(pbng_ctx *x, const pbng_csr *g, int32_t ng, pbng_side side, c
 
 int pbng_wing_batch(pbng_ctx *x, const pbng_csr *g, int32_t ng, const pbng_opts *opts, uint64_t *const *outs) {
     return batch_call(x, g, ng, 1, 0, opts, outs);
+}
+
+int pbng_autotune(pbng_ctx *x, const pbng_csr *g, int32_t kind, const pbng_opts *base, pbng_opts *best,
+                  double *ms_best) {
+    if (!x) return PBNG_E_ARG;
+    Ctx &c = x->c;
+    int rc = check_csr(g);
+    if (rc) return fail(c, rc, "bad graph arguments");
+    if (kind < 0 || kind > 2 || !best) return fail(c, PBNG_E_ARG, "bad autotune arguments");
+    CallScope scope(c);
+    return guarded(c, [&] {
+        c.timing_begin_call(false);
+        pbng_csr dg = device_graph(c, *g);
+        DevGraph G;
+        build_graph(c, dg, G);
+        const std::array<i64, 5> key{g->n_u, g->n_v, g->m, G.maxdeg, (i64)kind};
+        auto hit = c.tune_cache.find(key);
+        if (hit != c.tune_cache.end()) {
+            *best = hit->second.first;
+            if (ms_best) *ms_best = hit->second.second;
+            return;
+        }
+        const i64 nout = kind == 2 ? g->m : (kind == 0 ? g->n_u : g->n_v);
+        u64 *out = c.alloc<u64>(nout);
+        const size_t mk = c.arena.mark();
+        auto run = [&](const pbng_opts &o) {
+            c.stats = pbng_stats{};
+            auto t0 = std::chrono::steady_clock::now();
+            if (kind == 2)
+                wing_decompose(c, G, o, out);
+            else
+                tip_decompose(c, G, kind, o, out);
+            PBNG_HIP(hipStreamSynchronize(c.stream));
+            const double ms = ms_since(t0);
+            c.arena.release_to(mk);
+            return ms;
+        };
+        pbng_opts cur = default_opts(base);
+        cur.flags &= ~PBNG_F_KERNEL_TIMING;
+        run(cur);
+        double best_ms = run(cur);
+        auto try_knob = [&](int32_t pbng_opts::*field, std::initializer_list<int32_t> values) {
+            const int32_t keep = cur.*field;
+            int32_t win = keep;
+            for (int32_t v : values) {
+                if (v == keep) continue;
+                cur.*field = v;
+                const double ms = run(cur);
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    win = v;
+                }
+            }
+            cur.*field = win;
+        };
+        try_knob(&pbng_opts::dense_cut, {-1, 256, 1024, 4096});
+        if (kind != 2) try_knob(&pbng_opts::tile_w, {1 << 16, 1 << 18, 1 << 20, -1});
+        const int32_t p0 = cur.P > 0 ? cur.P : (kind == 2 ? 400 : 150);
+        try_knob(&pbng_opts::P, {std::max(1, p0 / 2), p0 * 2});
+        *best = cur;
+        if (ms_best) *ms_best = best_ms;
+        c.tune_cache[key] = {cur, best_ms};
+    });
 }
 
 int pbng_tip_features(pbng_ctx *x, const pbng_csr *g, pbng_side side, float *feat) {

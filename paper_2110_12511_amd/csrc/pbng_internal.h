@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <array>
 #include <map>
 #include <stdexcept>
 #include <string>
@@ -46,6 +47,8 @@ struct Arena {
     size_t bytes_held = 0;
     void *take(size_t bytes);
     void release_all();  // back to the free list (end of a call)
+    size_t mark() const { return in_use.size(); }
+    void release_to(size_t mark);  // blocks taken after `mark` back to the free list
     void destroy();      // hipFree everything
 };
 
@@ -74,9 +77,14 @@ struct Ctx {
     float *mlp_p = nullptr, *mlp_m = nullptr, *mlp_v = nullptr, *mlp_g = nullptr, *mlp_acc = nullptr;
     int mlp_t = 0;
     bool mlp_ready = false;
+    // autotuner: best settings and their time per graph signature
+    std::map<std::array<i64, 5>, std::pair<pbng_opts, double>> tune_cache;
     // stream used only to capture round graphs (replayed on `stream`)
     hipStream_t cap_stream = nullptr;
     hipStream_t capture_stream();
+    // second stream for work that overlaps the context stream's
+    hipStream_t aux_stream = nullptr;
+    hipStream_t aux();
     template <class T>
     T *alloc(size_t n) {
         return static_cast<T *>(arena.take((n ? n : 1) * sizeof(T)));
@@ -181,6 +189,38 @@ struct GraphExec {
     GraphExec &operator=(const GraphExec &) = delete;
     ~GraphExec() {
         if (e) (void)hipGraphExecDestroy(e);
+    }
+};
+
+// Work forked onto the context's second stream and joined back: fork()
+// makes the second stream wait for everything queued so far on the context
+// stream; join() makes the context stream wait for the second stream.
+struct StreamJoin {
+    Ctx &c;
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    bool forked = false;
+    explicit StreamJoin(Ctx &cc) : c(cc) {}
+    StreamJoin(const StreamJoin &) = delete;
+    StreamJoin &operator=(const StreamJoin &) = delete;
+    void fork() {
+        aux = c.aux();
+        PBNG_HIP(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
+        PBNG_HIP(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
+        PBNG_HIP(hipEventRecord(ev_fork, c.stream));
+        PBNG_HIP(hipStreamWaitEvent(aux, ev_fork, 0));
+        forked = true;
+    }
+    void join() {
+        if (!forked) return;
+        PBNG_HIP(hipEventRecord(ev_join, aux));
+        PBNG_HIP(hipStreamWaitEvent(c.stream, ev_join, 0));
+        forked = false;
+    }
+    ~StreamJoin() {
+        if (aux) (void)hipStreamSynchronize(aux);
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
+        if (ev_join) (void)hipEventDestroy(ev_join);
     }
 };
 

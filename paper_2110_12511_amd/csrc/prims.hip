@@ -42,6 +42,13 @@ void Arena::release_all() {
     in_use.clear();
 }
 
+void Arena::release_to(size_t mark) {
+    while (in_use.size() > mark) {
+        free_blocks.insert({in_use.back().second, in_use.back().first});
+        in_use.pop_back();
+    }
+}
+
 void Arena::destroy() {
     release_all();
     for (auto &kv : free_blocks) (void)hipFree(kv.second);
@@ -64,6 +71,11 @@ hipStream_t Ctx::capture_stream() {
     // non-blocking, default priority
     if (!cap_stream) PBNG_HIP(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
     return cap_stream;
+}
+
+hipStream_t Ctx::aux() {
+    if (!aux_stream) PBNG_HIP(hipStreamCreateWithFlags(&aux_stream, hipStreamNonBlocking));
+    return aux_stream;
 }
 
 void Ctx::kbegin(int cls) {

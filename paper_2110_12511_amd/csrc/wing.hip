@@ -634,6 +634,167 @@ __global__ __launch_bounds__(256) void k_wing_fd(WFdArgs a) {
     tl.flush(a.kc, a.work);
 }
 
+// ------------------------------------------------------------------ large partitions
+//
+// A partition whose work would keep one workgroup busy for long is peeled
+// level by level with device-wide kernels instead (the level-batch rule and
+// the updates are those of k_wing_fd): every level is one minimum reduction,
+// one batch selection, one pass over the batch's links, one over the touched
+// instances' pairs, the bloom-number update and the clamp.  Levels are
+// issued in groups without waiting; levels after the last find nothing to do.
+
+struct BigCtl {
+    u64 kmin;
+    u32 nb, ntouch;
+    i64 remaining;
+    u64 levels;
+};
+
+constexpr u64 WFD_BIG_WORK = u64(1) << 24;  // work units above which a partition goes device-wide
+constexpr int WFD_BIG_GROUP = 8;            // levels issued per host check
+
+__global__ void wb_init(const i32 *es, i64 base, i32 ne, const u64 *init, i64 *lsup, unsigned char *lst, BigCtl *ctl) {
+    for (i32 k = blockIdx.x * blockDim.x + threadIdx.x; k < ne; k += gridDim.x * blockDim.x) {
+        lsup[k] = (i64)init[es[base + k]];
+        lst[k] = 1;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ctl->kmin = ~0ull;
+        ctl->nb = ctl->ntouch = 0;
+        ctl->remaining = ne;
+        ctl->levels = 0;
+    }
+}
+
+__global__ __launch_bounds__(256) void wb_min(const i64 *lsup, const unsigned char *lst, i32 ne, BigCtl *ctl) {
+    __shared__ u64 s_red[256 / WAVE];
+    u64 mn = ~0ull;
+    for (i32 k = blockIdx.x * blockDim.x + threadIdx.x; k < ne; k += gridDim.x * blockDim.x)
+        if (lst[k] == 1) {
+            const u64 v = (u64)lsup[k];
+            mn = v < mn ? v : mn;
+        }
+    mn = block_min_u64<256>(mn, s_red);
+    if (threadIdx.x == 0 && mn != ~0ull) atomicMin((unsigned long long *)&ctl->kmin, (unsigned long long)mn);
+}
+
+__global__ void wb_batch(const i32 *es, i64 base, i32 ne, const i64 *lsup, unsigned char *lst, i32 *lbatch, u64 *theta,
+                         BigCtl *ctl) {
+    const u64 kmin = ctl->kmin;
+    for (i32 k = blockIdx.x * blockDim.x + threadIdx.x; k < ne; k += gridDim.x * blockDim.x) {
+        if (lst[k] == 1 && (u64)lsup[k] == kmin) {
+            const u32 p = atomicAdd(&ctl->nb, 1u);
+            lbatch[p] = k;
+            lst[k] = 2;
+            theta[es[base + k]] = kmin;
+        }
+    }
+}
+
+// one wave per batch edge: twin updates (Algorithm 6 reading: k_B - 1) and
+// the first touch of every instance
+__global__ void wb_links(const WFdArgs a, i32 pid, i64 base, i64 *lsup, const unsigned char *lst, const i32 *lbatch,
+                         u32 *ltouch, BigCtl *ctl) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const i64 wave = (blockIdx.x * (i64)blockDim.x + threadIdx.x) / WAVE;
+    const i64 nwaves = (i64)gridDim.x * blockDim.x / WAVE;
+    const u32 nb = ctl->nb;
+    u64 work = 0;
+    for (i64 j = wave; j < nb; j += nwaves) {
+        const i32 k = lbatch[j];
+        const i32 e = a.es[base + k];
+        for (i64 li = a.loff[base + k] + lane; li < a.loff[base + k + 1]; li += WAVE) {
+            const i32 et = a.ltwin[li];
+            const u32 t = a.linst[li];
+            ++work;
+            unsigned char ts = 3;
+            i32 tk = -1;
+            if (a.part[et] == pid) {
+                tk = a.eloc[et];
+                ts = lst[tk];
+            }
+            if (ts == 0) continue;
+            if (ts == 2 && et > e) continue;
+            if (ts == 1) {
+                const u64 kb = a.ik[t];
+                if (kb > 1) atomicAdd((unsigned long long *)&lsup[tk], (unsigned long long)(0ull - (kb - 1)));
+            }
+            if (atomicAdd(&a.icount[t], 1u) == 0) {
+                const u32 p = atomicAdd(&ctl->ntouch, 1u);
+                ltouch[p] = t;
+            }
+        }
+    }
+    for (int d = WAVE / 2; d > 0; d >>= 1) work += __shfl_down(work, d, WAVE);
+    if (lane == 0 && work) atomicAdd((unsigned long long *)a.work, (unsigned long long)work);
+}
+
+// one wave per touched instance: surviving pairs lose the instance's count
+__global__ void wb_inst(const WFdArgs a, i32 pid, i64 *lsup, const unsigned char *lst, const u32 *ltouch, BigCtl *ctl) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const i64 wave = (blockIdx.x * (i64)blockDim.x + threadIdx.x) / WAVE;
+    const i64 nwaves = (i64)gridDim.x * blockDim.x / WAVE;
+    const u32 nt = ctl->ntouch;
+    u64 work = 0;
+    for (i64 j = wave; j < nt; j += nwaves) {
+        const u32 t = ltouch[j];
+        const u64 cnt = a.icount[t];
+        const i64 p0 = a.ipstart[t];
+        const i64 p1 = p0 + a.iplen[t];
+        for (i64 pq = p0 + lane; pq < p1; pq += WAVE) {
+            const i32 e1 = a.fpair[2 * pq];
+            if (e1 < 0) continue;
+            const i32 e2 = a.fpair[2 * pq + 1];
+            ++work;
+            const bool in1 = a.part[e1] == pid, in2 = a.part[e2] == pid;
+            const i32 k1 = in1 ? a.eloc[e1] : -1, k2 = in2 ? a.eloc[e2] : -1;
+            const unsigned char s1 = in1 ? lst[k1] : (unsigned char)1;
+            const unsigned char s2 = in2 ? lst[k2] : (unsigned char)1;
+            if (s1 != 1 || s2 != 1) {
+                a.fpair[2 * pq] = -1;
+                continue;
+            }
+            if (in1) atomicAdd((unsigned long long *)&lsup[k1], (unsigned long long)(0ull - cnt));
+            if (in2) atomicAdd((unsigned long long *)&lsup[k2], (unsigned long long)(0ull - cnt));
+        }
+    }
+    for (int d = WAVE / 2; d > 0; d >>= 1) work += __shfl_down(work, d, WAVE);
+    if (lane == 0 && work) atomicAdd((unsigned long long *)a.work, (unsigned long long)work);
+}
+
+__global__ void wb_reset(const WFdArgs a, const u32 *ltouch, const BigCtl *ctl) {
+    const u32 nt = ctl->ntouch;
+    for (u32 j = blockIdx.x * blockDim.x + threadIdx.x; j < nt; j += gridDim.x * blockDim.x) {
+        const u32 t = ltouch[j];
+        const u32 cnt = a.icount[t];
+        a.icount[t] = 0;
+        a.ik[t] -= cnt;
+    }
+}
+
+__global__ void wb_clamp(i64 *lsup, unsigned char *lst, i32 ne, const BigCtl *ctl) {
+    const u64 kmin = ctl->kmin;
+    if (kmin == ~0ull) return;
+    for (i32 k = blockIdx.x * blockDim.x + threadIdx.x; k < ne; k += gridDim.x * blockDim.x) {
+        const unsigned char st = lst[k];
+        if (st == 2) {
+            lst[k] = 0;
+        } else if (st == 1 && lsup[k] < (i64)kmin) {
+            lsup[k] = (i64)kmin;
+        }
+    }
+}
+
+__global__ void wb_next(BigCtl *ctl) {
+    if (ctl->nb) {
+        ctl->remaining -= ctl->nb;
+        ctl->levels += 1;
+    }
+    ctl->kmin = ~0ull;
+    ctl->nb = 0;
+    ctl->ntouch = 0;
+}
+
 // ------------------------------------------------------------------ host
 
 static double wnow_ms() {
@@ -955,7 +1116,26 @@ void wing_decompose(Ctx &c, const DevGraph &G, const pbng_opts &o, u64 *theta) {
     c.stats.ms_fd_prep = t3 - t2;
 
     // ---- fine-grained phase
-    const int fdblocks = (int)std::min<i64>(np, (i64)c.num_cu * 2);
+    // partitions in LPT order; the largest (work above WFD_BIG_WORK) are
+    // peeled device-wide on the context stream while the persistent kernel
+    // takes the rest from the queue on a second stream
+    std::vector<i32> q_h(np);
+    std::vector<u64> w_h(np);
+    std::vector<i64> eo_h(np + 1);
+    PBNG_HIP(hipMemcpyAsync(q_h.data(), queue, sizeof(i32) * np, hipMemcpyDeviceToHost, s));
+    PBNG_HIP(hipMemcpyAsync(w_h.data(), work, sizeof(u64) * np, hipMemcpyDeviceToHost, s));
+    PBNG_HIP(hipMemcpyAsync(eo_h.data(), epoff, sizeof(i64) * (np + 1), hipMemcpyDeviceToHost, s));
+    PBNG_HIP(hipStreamSynchronize(s));
+    const bool big_off = o.wide_work < 0;
+    const u64 big_work = o.wide_work > 0 ? (u64)o.wide_work : WFD_BIG_WORK;
+    u32 nbig = 0;
+    i64 big_ne = 1;
+    while (!big_off && (i32)nbig < np && w_h[q_h[nbig]] >= big_work) {
+        big_ne = std::max<i64>(big_ne, eo_h[q_h[nbig] + 1] - eo_h[q_h[nbig]]);
+        ++nbig;
+    }
+    const i32 nsmall = np - (i32)nbig;
+    const int fdblocks = (int)std::max<i64>(1, std::min<i64>(nsmall, (i64)c.num_cu * 2));
     WFdArgs fa{};
     fa.es = es;
     fa.epoff = epoff;
@@ -972,7 +1152,7 @@ void wing_decompose(Ctx &c, const DevGraph &G, const pbng_opts &o, u64 *theta) {
     fa.queue = queue;
     fa.np = np;
     fa.head = c.alloc<u32>(1);
-    PBNG_HIP(hipMemsetAsync(fa.head, 0, sizeof(u32), s));
+    PBNG_HIP(hipMemcpyAsync(fa.head, &nbig, sizeof(u32), hipMemcpyHostToDevice, s));
     fa.init = init;
     fa.theta = theta;
     fa.maxne = maxne;
@@ -989,21 +1169,62 @@ void wing_decompose(Ctx &c, const DevGraph &G, const pbng_opts &o, u64 *theta) {
         fa.levels = c.alloc<u32>(np);
         PBNG_HIP(hipMemsetAsync(fa.levels, 0, sizeof(u32) * np, s));
     }
+    // big-partition scratch
+    i64 *blsup = c.alloc<i64>(big_ne);
+    unsigned char *blst = c.alloc<unsigned char>(big_ne);
+    i32 *blbatch = c.alloc<i32>(big_ne);
+    u32 *bltouch = c.alloc<u32>(maxinst);
+    BigCtl *bctl = c.alloc<BigCtl>(1);
+    std::vector<u64> big_levels(nbig, 0);
     c.kbegin(PBNG_K_FD);
-    hipLaunchKernelGGL(k_wing_fd, dim3(fdblocks), dim3(256), 0, s, fa);
+    StreamJoin join(c);
+    if (nsmall > 0) {
+        join.fork();
+        hipLaunchKernelGGL(k_wing_fd, dim3(fdblocks), dim3(256), 0, join.aux, fa);
+        PBNG_LAUNCH_CHECK();
+    }
+    const int gb = c.num_cu * 4;
+    for (u32 b = 0; b < nbig; ++b) {
+        const i32 pid = q_h[b];
+        const i64 base = eo_h[pid];
+        const i32 ne = (i32)(eo_h[pid + 1] - base);
+        hipLaunchKernelGGL(wb_init, dim3(gb), dim3(256), 0, s, (const i32 *)es, base, ne, (const u64 *)init, blsup, blst, bctl);
+        PBNG_LAUNCH_CHECK();
+        i64 rem = ne;
+        // every level retires at least one edge
+        for (i64 groups = 0; rem > 0; ++groups) {
+            if (groups > (i64)ne / WFD_BIG_GROUP + 2) throw Error(PBNG_E_DEVICE, "device-wide partition did not finish");
+            for (int l = 0; l < WFD_BIG_GROUP; ++l) {
+                hipLaunchKernelGGL(wb_min, dim3(gb), dim3(256), 0, s, (const i64 *)blsup, (const unsigned char *)blst, ne, bctl);
+                hipLaunchKernelGGL(wb_batch, dim3(gb), dim3(256), 0, s, (const i32 *)es, base, ne, (const i64 *)blsup, blst,
+                                   blbatch, theta, bctl);
+                hipLaunchKernelGGL(wb_links, dim3(gb), dim3(256), 0, s, fa, pid, base, blsup, (const unsigned char *)blst,
+                                   (const i32 *)blbatch, bltouch, bctl);
+                hipLaunchKernelGGL(wb_inst, dim3(gb), dim3(256), 0, s, fa, pid, blsup, (const unsigned char *)blst,
+                                   (const u32 *)bltouch, bctl);
+                hipLaunchKernelGGL(wb_reset, dim3(gb), dim3(256), 0, s, fa, (const u32 *)bltouch, (const BigCtl *)bctl);
+                hipLaunchKernelGGL(wb_clamp, dim3(gb), dim3(256), 0, s, blsup, blst, ne, (const BigCtl *)bctl);
+                hipLaunchKernelGGL(wb_next, dim3(1), dim3(1), 0, s, bctl);
+                PBNG_LAUNCH_CHECK();
+            }
+            BigCtl h;
+            PBNG_HIP(hipMemcpyAsync(&h, bctl, sizeof(BigCtl), hipMemcpyDeviceToHost, s));
+            PBNG_HIP(hipStreamSynchronize(s));
+            rem = h.remaining;
+            big_levels[b] = h.levels;
+        }
+    }
+    join.join();
     c.kend(PBNG_K_FD);
-    PBNG_LAUNCH_CHECK();
+    c.stats.fd_wide = nbig;
     if (trace) {
         std::vector<u32> lv_h(np);
-        std::vector<i64> eo_h(np + 1);
-        std::vector<u64> wk_h(np);
         PBNG_HIP(hipMemcpyAsync(lv_h.data(), fa.levels, sizeof(u32) * np, hipMemcpyDeviceToHost, s));
-        PBNG_HIP(hipMemcpyAsync(eo_h.data(), epoff, sizeof(i64) * (np + 1), hipMemcpyDeviceToHost, s));
-        PBNG_HIP(hipMemcpyAsync(wk_h.data(), work, sizeof(u64) * np, hipMemcpyDeviceToHost, s));
         PBNG_HIP(hipStreamSynchronize(s));
+        for (u32 b = 0; b < nbig; ++b) lv_h[q_h[b]] = (u32)big_levels[b];
         for (int p = 0; p < np; ++p)
-            fprintf(stderr, "[pbng-trace] wing-fd part %d edges %lld levels %u work %llu\n", p, (long long)(eo_h[p + 1] - eo_h[p]),
-                    lv_h[p], (unsigned long long)wk_h[p]);
+            fprintf(stderr, "[pbng-trace] wing-fd part %d edges %lld levels %u work %llu%s\n", p, (long long)(eo_h[p + 1] - eo_h[p]),
+                    lv_h[p], (unsigned long long)w_h[p], w_h[p] >= big_work && !big_off ? " wide" : "");
     }
     c.stats.wedges_fd = read_scalar<u64>(c, fa.work);
     c.stats.ms_fd = wnow_ms() - t3;

@@ -154,3 +154,15 @@ def clustered():
 def test_tip_clustered_keys_overflow(ctx, clustered, P, tile_w):
     g, eu = clustered
     assert np.array_equal(gpu_tip(ctx, g, 0, P=P, tile_w=tile_w), eu)
+
+
+def test_autotune_tip_and_cache(ctx, cl_mid):
+    g, eu, ev = cl_mid
+    dg = pb.DeviceGraph.from_graph(g)
+    best, ms = ctx.autotune(dg, 0, pb.make_opts(P=40))
+    assert ms > 0 and best.P in (20, 40, 80)
+    assert np.array_equal(u64(pb.tip(ctx, dg, 0, best)), eu)
+    best2, ms2 = ctx.autotune(dg, 0, pb.make_opts(P=40))
+    assert (best2.P, best2.dense_cut, best2.tile_w, ms2) == (best.P, best.dense_cut, best.tile_w, ms)
+    bv, _ = ctx.autotune(dg, 1)
+    assert np.array_equal(u64(pb.tip(ctx, dg, 1, bv)), ev)

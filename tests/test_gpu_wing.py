@@ -95,3 +95,24 @@ def test_wing_host_rounds_match_graph_rounds(ctx, cl_wing, P):
     rho_graph = ctx.stats()["rho"]
     assert np.array_equal(gpu_wing(ctx, g, P=P, flags=pb.F_HOST_ROUNDS), exp)
     assert ctx.stats()["rho"] == rho_graph
+
+
+def test_autotune_wing(ctx, cl_wing):
+    g, exp = cl_wing
+    dg = pb.DeviceGraph.from_graph(g)
+    best, ms = ctx.autotune(dg, 2)
+    assert ms > 0
+    assert np.array_equal(u64(pb.wing(ctx, dg, best)), exp)
+
+
+@pytest.mark.parametrize("wide_work", [-1, 1, 5000])
+def test_wing_device_wide_partitions(ctx, cl_wing, wide_work):
+    """Partitions peeled by device-wide level kernels (all of them at
+    wide_work = 1) give the same numbers as the persistent kernel."""
+    g, exp = cl_wing
+    assert np.array_equal(gpu_wing(ctx, g, P=60, wide_work=wide_work), exp)
+    st = ctx.stats()
+    if wide_work == -1:
+        assert st["fd_wide"] == 0
+    if wide_work == 1:
+        assert st["fd_wide"] >= st["partitions"] - 1
