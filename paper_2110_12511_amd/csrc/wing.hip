@@ -643,156 +643,213 @@ __global__ __launch_bounds__(256) void k_wing_fd(WFdArgs a) {
 // instances' pairs, the bloom-number update and the clamp.  Levels are
 // issued in groups without waiting; levels after the last find nothing to do.
 
-struct BigCtl {
-    u64 kmin;
+// All wide partitions advance together: one step peels the current minimum
+// level of every wide partition that still has edges, so the number of steps
+// is the largest level count among them, not the sum.  State is indexed by
+// position in the partition-grouped edge order (es), so an edge e of
+// partition p sits at epoff[p] + eloc[e].  Scans over a partition's edges use
+// a 2-D grid: blockIdx.y is the wide partition, blockIdx.x strides over its
+// edges.
+
+struct WideCtl {
     u32 nb, ntouch;
-    i64 remaining;
-    u64 levels;
+    u64 alive;  // edges of wide partitions not yet peeled
+    u64 steps;
 };
 
-constexpr u64 WFD_BIG_WORK = u64(1) << 24;  // work units above which a partition goes device-wide
-constexpr int WFD_BIG_GROUP = 8;            // levels issued per host check
+constexpr u64 WFD_BIG_WORK = u64(1) << 24;  // estimated work above which a partition goes device-wide
+constexpr int WFD_BIG_GROUP = 8;            // steps issued per host check
 
-__global__ void wb_init(const i32 *es, i64 base, i32 ne, const u64 *init, i64 *lsup, unsigned char *lst, BigCtl *ctl) {
-    for (i32 k = blockIdx.x * blockDim.x + threadIdx.x; k < ne; k += gridDim.x * blockDim.x) {
-        lsup[k] = (i64)init[es[base + k]];
-        lst[k] = 1;
+struct WideArgs {
+    const i32 *wpid;    // wide partition -> partition id
+    const i64 *epoff;
+    const i32 *es;
+    const i32 *part;
+    const i32 *eloc;
+    const i32 *widx;    // partition id -> wide index or -1
+    i64 *lsup;          // [m] by position
+    unsigned char *lst; // [m] by position: 1 alive, 2 batch, 0 peeled
+    u64 *kmin;          // [nw] current level
+    u32 *nbw;           // [nw] edges peeled this step
+    u64 *remaining;     // [nw]
+    u64 *levels;        // [nw]
+    i32 *batch;         // positions peeled this step
+    u32 *touch;         // instances touched this step
+    WideCtl *ctl;
+    const u64 *init;
+    u64 *theta;
+    i32 nw;
+};
+
+__global__ void wm_init(WideArgs a) {
+    const i32 w = blockIdx.y;
+    const i32 pid = a.wpid[w];
+    const i64 b = a.epoff[pid], e = a.epoff[pid + 1];
+    for (i64 q = b + blockIdx.x * (i64)blockDim.x + threadIdx.x; q < e; q += (i64)gridDim.x * blockDim.x) {
+        a.lsup[q] = (i64)a.init[a.es[q]];
+        a.lst[q] = 1;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        ctl->kmin = ~0ull;
-        ctl->nb = ctl->ntouch = 0;
-        ctl->remaining = ne;
-        ctl->levels = 0;
+        a.kmin[w] = ~0ull;
+        a.nbw[w] = 0;
+        a.remaining[w] = (u64)(e - b);
+        a.levels[w] = 0;
+        atomicAdd((unsigned long long *)&a.ctl->alive, (unsigned long long)(e - b));
     }
 }
 
-__global__ __launch_bounds__(256) void wb_min(const i64 *lsup, const unsigned char *lst, i32 ne, BigCtl *ctl) {
+__global__ __launch_bounds__(256) void wm_min(WideArgs a) {
     __shared__ u64 s_red[256 / WAVE];
+    const i32 w = blockIdx.y;
+    if (a.remaining[w] == 0) return;  // block-uniform
+    const i32 pid = a.wpid[w];
+    const i64 b = a.epoff[pid], e = a.epoff[pid + 1];
     u64 mn = ~0ull;
-    for (i32 k = blockIdx.x * blockDim.x + threadIdx.x; k < ne; k += gridDim.x * blockDim.x)
-        if (lst[k] == 1) {
-            const u64 v = (u64)lsup[k];
+    for (i64 q = b + blockIdx.x * (i64)blockDim.x + threadIdx.x; q < e; q += (i64)gridDim.x * blockDim.x)
+        if (a.lst[q] == 1) {
+            const u64 v = (u64)a.lsup[q];
             mn = v < mn ? v : mn;
         }
     mn = block_min_u64<256>(mn, s_red);
-    if (threadIdx.x == 0 && mn != ~0ull) atomicMin((unsigned long long *)&ctl->kmin, (unsigned long long)mn);
+    if (threadIdx.x == 0 && mn != ~0ull) atomicMin((unsigned long long *)&a.kmin[w], (unsigned long long)mn);
 }
 
-__global__ void wb_batch(const i32 *es, i64 base, i32 ne, const i64 *lsup, unsigned char *lst, i32 *lbatch, u64 *theta,
-                         BigCtl *ctl) {
-    const u64 kmin = ctl->kmin;
-    for (i32 k = blockIdx.x * blockDim.x + threadIdx.x; k < ne; k += gridDim.x * blockDim.x) {
-        if (lst[k] == 1 && (u64)lsup[k] == kmin) {
-            const u32 p = atomicAdd(&ctl->nb, 1u);
-            lbatch[p] = k;
-            lst[k] = 2;
-            theta[es[base + k]] = kmin;
+__global__ void wm_batch(WideArgs a) {
+    const i32 w = blockIdx.y;
+    if (a.remaining[w] == 0) return;
+    const i32 pid = a.wpid[w];
+    const i64 b = a.epoff[pid], e = a.epoff[pid + 1];
+    const u64 kmin = a.kmin[w];
+    u32 cnt = 0;
+    for (i64 q = b + blockIdx.x * (i64)blockDim.x + threadIdx.x; q < e; q += (i64)gridDim.x * blockDim.x) {
+        if (a.lst[q] == 1 && (u64)a.lsup[q] == kmin) {
+            const u32 p = atomicAdd(&a.ctl->nb, 1u);
+            a.batch[p] = (i32)q;
+            a.lst[q] = 2;
+            a.theta[a.es[q]] = kmin;
+            ++cnt;
         }
     }
+    if (cnt) atomicAdd(&a.nbw[w], cnt);
 }
 
 // one wave per batch edge: twin updates (Algorithm 6 reading: k_B - 1) and
 // the first touch of every instance
-__global__ void wb_links(const WFdArgs a, i32 pid, i64 base, i64 *lsup, const unsigned char *lst, const i32 *lbatch,
-                         u32 *ltouch, BigCtl *ctl) {
+__global__ void wm_links(const WFdArgs f, WideArgs a) {
     const int lane = threadIdx.x & (WAVE - 1);
     const i64 wave = (blockIdx.x * (i64)blockDim.x + threadIdx.x) / WAVE;
     const i64 nwaves = (i64)gridDim.x * blockDim.x / WAVE;
-    const u32 nb = ctl->nb;
+    const u32 nb = a.ctl->nb;
     u64 work = 0;
     for (i64 j = wave; j < nb; j += nwaves) {
-        const i32 k = lbatch[j];
-        const i32 e = a.es[base + k];
-        for (i64 li = a.loff[base + k] + lane; li < a.loff[base + k + 1]; li += WAVE) {
-            const i32 et = a.ltwin[li];
-            const u32 t = a.linst[li];
+        const i64 q = a.batch[j];
+        const i32 e = a.es[q];
+        const i32 pid = a.part[e];
+        const i64 pbase = a.epoff[pid];
+        for (i64 li = f.loff[q] + lane; li < f.loff[q + 1]; li += WAVE) {
+            const i32 et = f.ltwin[li];
+            const u32 t = f.linst[li];
             ++work;
             unsigned char ts = 3;
-            i32 tk = -1;
+            i64 tq = -1;
             if (a.part[et] == pid) {
-                tk = a.eloc[et];
-                ts = lst[tk];
+                tq = pbase + a.eloc[et];
+                ts = a.lst[tq];
             }
             if (ts == 0) continue;
             if (ts == 2 && et > e) continue;
             if (ts == 1) {
-                const u64 kb = a.ik[t];
-                if (kb > 1) atomicAdd((unsigned long long *)&lsup[tk], (unsigned long long)(0ull - (kb - 1)));
+                const u64 kb = f.ik[t];
+                if (kb > 1) atomicAdd((unsigned long long *)&a.lsup[tq], (unsigned long long)(0ull - (kb - 1)));
             }
-            if (atomicAdd(&a.icount[t], 1u) == 0) {
-                const u32 p = atomicAdd(&ctl->ntouch, 1u);
-                ltouch[p] = t;
+            if (atomicAdd(&f.icount[t], 1u) == 0) {
+                const u32 p = atomicAdd(&a.ctl->ntouch, 1u);
+                a.touch[p] = t;
             }
         }
     }
     for (int d = WAVE / 2; d > 0; d >>= 1) work += __shfl_down(work, d, WAVE);
-    if (lane == 0 && work) atomicAdd((unsigned long long *)a.work, (unsigned long long)work);
+    if (lane == 0 && work) atomicAdd((unsigned long long *)f.work, (unsigned long long)work);
 }
 
 // one wave per touched instance: surviving pairs lose the instance's count
-__global__ void wb_inst(const WFdArgs a, i32 pid, i64 *lsup, const unsigned char *lst, const u32 *ltouch, BigCtl *ctl) {
+__global__ void wm_inst(const WFdArgs f, WideArgs a, const i32 *ipart) {
     const int lane = threadIdx.x & (WAVE - 1);
     const i64 wave = (blockIdx.x * (i64)blockDim.x + threadIdx.x) / WAVE;
     const i64 nwaves = (i64)gridDim.x * blockDim.x / WAVE;
-    const u32 nt = ctl->ntouch;
+    const u32 nt = a.ctl->ntouch;
     u64 work = 0;
     for (i64 j = wave; j < nt; j += nwaves) {
-        const u32 t = ltouch[j];
-        const u64 cnt = a.icount[t];
-        const i64 p0 = a.ipstart[t];
-        const i64 p1 = p0 + a.iplen[t];
+        const u32 t = a.touch[j];
+        const i32 pid = ipart[t];
+        const i64 pbase = a.epoff[pid];
+        const u64 cnt = f.icount[t];
+        const i64 p0 = f.ipstart[t];
+        const i64 p1 = p0 + f.iplen[t];
         for (i64 pq = p0 + lane; pq < p1; pq += WAVE) {
-            const i32 e1 = a.fpair[2 * pq];
+            const i32 e1 = f.fpair[2 * pq];
             if (e1 < 0) continue;
-            const i32 e2 = a.fpair[2 * pq + 1];
+            const i32 e2 = f.fpair[2 * pq + 1];
             ++work;
             const bool in1 = a.part[e1] == pid, in2 = a.part[e2] == pid;
-            const i32 k1 = in1 ? a.eloc[e1] : -1, k2 = in2 ? a.eloc[e2] : -1;
-            const unsigned char s1 = in1 ? lst[k1] : (unsigned char)1;
-            const unsigned char s2 = in2 ? lst[k2] : (unsigned char)1;
+            const i64 q1 = in1 ? pbase + a.eloc[e1] : -1, q2 = in2 ? pbase + a.eloc[e2] : -1;
+            const unsigned char s1 = in1 ? a.lst[q1] : (unsigned char)1;
+            const unsigned char s2 = in2 ? a.lst[q2] : (unsigned char)1;
             if (s1 != 1 || s2 != 1) {
-                a.fpair[2 * pq] = -1;
+                f.fpair[2 * pq] = -1;
                 continue;
             }
-            if (in1) atomicAdd((unsigned long long *)&lsup[k1], (unsigned long long)(0ull - cnt));
-            if (in2) atomicAdd((unsigned long long *)&lsup[k2], (unsigned long long)(0ull - cnt));
+            if (in1) atomicAdd((unsigned long long *)&a.lsup[q1], (unsigned long long)(0ull - cnt));
+            if (in2) atomicAdd((unsigned long long *)&a.lsup[q2], (unsigned long long)(0ull - cnt));
         }
     }
     for (int d = WAVE / 2; d > 0; d >>= 1) work += __shfl_down(work, d, WAVE);
-    if (lane == 0 && work) atomicAdd((unsigned long long *)a.work, (unsigned long long)work);
+    if (lane == 0 && work) atomicAdd((unsigned long long *)f.work, (unsigned long long)work);
 }
 
-__global__ void wb_reset(const WFdArgs a, const u32 *ltouch, const BigCtl *ctl) {
-    const u32 nt = ctl->ntouch;
+__global__ void wm_reset(const WFdArgs f, WideArgs a) {
+    const u32 nt = a.ctl->ntouch;
     for (u32 j = blockIdx.x * blockDim.x + threadIdx.x; j < nt; j += gridDim.x * blockDim.x) {
-        const u32 t = ltouch[j];
-        const u32 cnt = a.icount[t];
-        a.icount[t] = 0;
-        a.ik[t] -= cnt;
+        const u32 t = a.touch[j];
+        const u32 cnt = f.icount[t];
+        f.icount[t] = 0;
+        f.ik[t] -= cnt;
     }
 }
 
-__global__ void wb_clamp(i64 *lsup, unsigned char *lst, i32 ne, const BigCtl *ctl) {
-    const u64 kmin = ctl->kmin;
+__global__ void wm_clamp(WideArgs a) {
+    const i32 w = blockIdx.y;
+    if (a.remaining[w] == 0) return;
+    const u64 kmin = a.kmin[w];
     if (kmin == ~0ull) return;
-    for (i32 k = blockIdx.x * blockDim.x + threadIdx.x; k < ne; k += gridDim.x * blockDim.x) {
-        const unsigned char st = lst[k];
+    const i32 pid = a.wpid[w];
+    const i64 b = a.epoff[pid], e = a.epoff[pid + 1];
+    for (i64 q = b + blockIdx.x * (i64)blockDim.x + threadIdx.x; q < e; q += (i64)gridDim.x * blockDim.x) {
+        const unsigned char st = a.lst[q];
         if (st == 2) {
-            lst[k] = 0;
-        } else if (st == 1 && lsup[k] < (i64)kmin) {
-            lsup[k] = (i64)kmin;
+            a.lst[q] = 0;
+        } else if (st == 1 && a.lsup[q] < (i64)kmin) {
+            a.lsup[q] = (i64)kmin;
         }
     }
 }
 
-__global__ void wb_next(BigCtl *ctl) {
-    if (ctl->nb) {
-        ctl->remaining -= ctl->nb;
-        ctl->levels += 1;
+__global__ void wm_next(WideArgs a) {
+    for (i32 w = blockIdx.x * blockDim.x + threadIdx.x; w < a.nw; w += gridDim.x * blockDim.x) {
+        const u32 nb = a.nbw[w];
+        if (nb) {
+            a.remaining[w] -= nb;
+            a.levels[w] += 1;
+            atomicAdd((unsigned long long *)&a.ctl->alive, (unsigned long long)(0ull - (u64)nb));
+        }
+        a.nbw[w] = 0;
+        a.kmin[w] = ~0ull;
     }
-    ctl->kmin = ~0ull;
-    ctl->nb = 0;
-    ctl->ntouch = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        a.ctl->nb = 0;
+        a.ctl->ntouch = 0;
+        a.ctl->steps += 1;
+    }
 }
 
 // ------------------------------------------------------------------ host
@@ -1129,7 +1186,7 @@ void wing_decompose(Ctx &c, const DevGraph &G, const pbng_opts &o, u64 *theta) {
     const bool big_off = o.wide_work < 0;
     const u64 big_work = o.wide_work > 0 ? (u64)o.wide_work : WFD_BIG_WORK;
     u32 nbig = 0;
-    i64 big_ne = 1;
+    i64 big_ne = 1;  // edges of the largest wide partition
     while (!big_off && (i32)nbig < np && w_h[q_h[nbig]] >= big_work) {
         big_ne = std::max<i64>(big_ne, eo_h[q_h[nbig] + 1] - eo_h[q_h[nbig]]);
         ++nbig;
@@ -1169,12 +1226,11 @@ void wing_decompose(Ctx &c, const DevGraph &G, const pbng_opts &o, u64 *theta) {
         fa.levels = c.alloc<u32>(np);
         PBNG_HIP(hipMemsetAsync(fa.levels, 0, sizeof(u32) * np, s));
     }
-    // big-partition scratch
-    i64 *blsup = c.alloc<i64>(big_ne);
-    unsigned char *blst = c.alloc<unsigned char>(big_ne);
-    i32 *blbatch = c.alloc<i32>(big_ne);
-    u32 *bltouch = c.alloc<u32>(maxinst);
-    BigCtl *bctl = c.alloc<BigCtl>(1);
+    // wide-partition state
+    WideArgs wa{};
+    std::vector<i32> wpid_h(q_h.begin(), q_h.begin() + nbig);
+    std::vector<i32> widx_h(np, -1);
+    for (u32 b = 0; b < nbig; ++b) widx_h[q_h[b]] = (i32)b;
     std::vector<u64> big_levels(nbig, 0);
     c.kbegin(PBNG_K_FD);
     StreamJoin join(c);
@@ -1183,36 +1239,54 @@ void wing_decompose(Ctx &c, const DevGraph &G, const pbng_opts &o, u64 *theta) {
         hipLaunchKernelGGL(k_wing_fd, dim3(fdblocks), dim3(256), 0, join.aux, fa);
         PBNG_LAUNCH_CHECK();
     }
-    const int gb = c.num_cu * 4;
-    for (u32 b = 0; b < nbig; ++b) {
-        const i32 pid = q_h[b];
-        const i64 base = eo_h[pid];
-        const i32 ne = (i32)(eo_h[pid + 1] - base);
-        hipLaunchKernelGGL(wb_init, dim3(gb), dim3(256), 0, s, (const i32 *)es, base, ne, (const u64 *)init, blsup, blst, bctl);
+    if (nbig > 0) {
+        i32 *wpid = c.alloc<i32>(nbig);
+        i32 *widx = c.alloc<i32>(np);
+        PBNG_HIP(hipMemcpy(wpid, wpid_h.data(), sizeof(i32) * nbig, hipMemcpyHostToDevice));
+        PBNG_HIP(hipMemcpy(widx, widx_h.data(), sizeof(i32) * np, hipMemcpyHostToDevice));
+        wa.wpid = wpid;
+        wa.epoff = epoff;
+        wa.es = es;
+        wa.part = part;
+        wa.eloc = eloc;
+        wa.widx = widx;
+        wa.lsup = c.alloc<i64>(m);
+        wa.lst = c.alloc<unsigned char>(m);
+        wa.kmin = c.alloc<u64>(nbig);
+        wa.nbw = c.alloc<u32>(nbig);
+        wa.remaining = c.alloc<u64>(nbig);
+        wa.levels = c.alloc<u64>(nbig);
+        wa.batch = c.alloc<i32>(m);
+        wa.touch = c.alloc<u32>(std::max<i64>(ninst, 1));
+        wa.ctl = c.alloc<WideCtl>(1);
+        wa.init = init;
+        wa.theta = theta;
+        wa.nw = (i32)nbig;
+        PBNG_HIP(hipMemsetAsync(wa.ctl, 0, sizeof(WideCtl), s));
+        const dim3 g2((unsigned)std::max<i64>(1, std::min<i64>((big_ne + 1023) / 1024, 64)), nbig);
+        const int gb = c.num_cu * 4;
+        hipLaunchKernelGGL(wm_init, g2, dim3(256), 0, s, wa);
         PBNG_LAUNCH_CHECK();
-        i64 rem = ne;
-        // every level retires at least one edge
-        for (i64 groups = 0; rem > 0; ++groups) {
-            if (groups > (i64)ne / WFD_BIG_GROUP + 2) throw Error(PBNG_E_DEVICE, "device-wide partition did not finish");
+        u64 alive = 1;
+        // every step retires at least one edge of every unfinished partition
+        for (i64 groups = 0; alive > 0; ++groups) {
+            if (groups > big_ne / WFD_BIG_GROUP + 2) throw Error(PBNG_E_DEVICE, "wide partitions did not finish");
             for (int l = 0; l < WFD_BIG_GROUP; ++l) {
-                hipLaunchKernelGGL(wb_min, dim3(gb), dim3(256), 0, s, (const i64 *)blsup, (const unsigned char *)blst, ne, bctl);
-                hipLaunchKernelGGL(wb_batch, dim3(gb), dim3(256), 0, s, (const i32 *)es, base, ne, (const i64 *)blsup, blst,
-                                   blbatch, theta, bctl);
-                hipLaunchKernelGGL(wb_links, dim3(gb), dim3(256), 0, s, fa, pid, base, blsup, (const unsigned char *)blst,
-                                   (const i32 *)blbatch, bltouch, bctl);
-                hipLaunchKernelGGL(wb_inst, dim3(gb), dim3(256), 0, s, fa, pid, blsup, (const unsigned char *)blst,
-                                   (const u32 *)bltouch, bctl);
-                hipLaunchKernelGGL(wb_reset, dim3(gb), dim3(256), 0, s, fa, (const u32 *)bltouch, (const BigCtl *)bctl);
-                hipLaunchKernelGGL(wb_clamp, dim3(gb), dim3(256), 0, s, blsup, blst, ne, (const BigCtl *)bctl);
-                hipLaunchKernelGGL(wb_next, dim3(1), dim3(1), 0, s, bctl);
+                hipLaunchKernelGGL(wm_min, g2, dim3(256), 0, s, wa);
+                hipLaunchKernelGGL(wm_batch, g2, dim3(256), 0, s, wa);
+                hipLaunchKernelGGL(wm_links, dim3(gb), dim3(256), 0, s, fa, wa);
+                hipLaunchKernelGGL(wm_inst, dim3(gb), dim3(256), 0, s, fa, wa, (const i32 *)ipart);
+                hipLaunchKernelGGL(wm_reset, dim3(gb), dim3(256), 0, s, fa, wa);
+                hipLaunchKernelGGL(wm_clamp, g2, dim3(256), 0, s, wa);
+                hipLaunchKernelGGL(wm_next, dim3(std::max<i64>(1, (nbig + 255) / 256)), dim3(256), 0, s, wa);
                 PBNG_LAUNCH_CHECK();
             }
-            BigCtl h;
-            PBNG_HIP(hipMemcpyAsync(&h, bctl, sizeof(BigCtl), hipMemcpyDeviceToHost, s));
+            WideCtl h;
+            PBNG_HIP(hipMemcpyAsync(&h, wa.ctl, sizeof(WideCtl), hipMemcpyDeviceToHost, s));
             PBNG_HIP(hipStreamSynchronize(s));
-            rem = h.remaining;
-            big_levels[b] = h.levels;
+            alive = h.alive;
         }
+        PBNG_HIP(hipMemcpyAsync(big_levels.data(), wa.levels, sizeof(u64) * nbig, hipMemcpyDeviceToHost, s));
     }
     join.join();
     c.kend(PBNG_K_FD);
