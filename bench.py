@@ -30,6 +30,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "wedges/s + tip/wing decomposition time, learned vs plain CD bounds, 1 GPU"
 HBM_PEAK_GBS = 8000.0
+# kernel behind each timed class that holds a single kernel
+CLASS_KERNEL = {"tip_hrange": "k_tip_peel_hrange<14>", "fd": "k_tip_fd / k_wing_fd", "dense": "m_gram"}
 
 WORKLOADS = {
     # name: (graph config, kind, P)
@@ -89,6 +91,30 @@ def copy_probe(torch, mib=1024, reps=5):
     del src, dst
     return dict(kernel="int32 negate", bytes_per_launch=2 * mib * (1 << 20), ms=round(ms, 4),
                 gbs=round(2 * mib * (1 << 20) / (ms / 1e3) / 1e9, 1))
+
+
+def profile_traffic(kernel_class, workload):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    counter summary (FETCH_SIZE and WRITE_SIZE scaled by a copy kernel's), or
+    None when there is none or the kernel's sources changed since."""
+    import re
+
+    names = {"tip_hrange": "k_tip_peel_hrange"}
+    if kernel_class not in names:
+        return None
+    path = os.path.join(ROOT, "profiles", f"{names[kernel_class]}__{workload}.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"traffic_bytes_per_launch: (\d+)", text)
+    h = re.search(r"source_sha256: ([0-9a-f]+)", text)
+    if not m or not h:
+        return None
+    src = b"".join(open(os.path.join(ROOT, "paper_2110_12511_amd", "csrc", f), "rb").read()
+                   for f in ("tip.hip", "dev_common.h"))
+    if hashlib.sha256(src).hexdigest() != h.group(1):
+        return None
+    return int(m.group(1))
 
 
 def cpu_baseline(graph_cfg, kind, budget_s):
@@ -188,8 +214,9 @@ def main():
     dom = max(agg, key=lambda n: agg[n]["ms"])
     d = agg[dom]
     achieved = d["bytes"] / (d["ms"] / 1e3) / 1e9 if d["ms"] > 0 else 0.0
-    roofline = dict(bound="hbm", kernel=dom, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+    roofline = dict(bound="hbm", kernel=CLASS_KERNEL.get(dom, dom), kernel_class=dom, achieved=round(achieved, 1),
+                    peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=profile_traffic(dom, args.workload),
                     avg_launch_ms=round(d["ms"] / max(d["launches"], 1), 4), launches=d["launches"],
                     algorithmic_bytes=d["bytes"], wedges=d["wedges"],
                     kernel_wedges_per_s=round(d["wedges"] / (d["ms"] / 1e3), 1) if d["ms"] > 0 else 0.0)

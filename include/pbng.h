@@ -100,7 +100,9 @@ enum {
     PBNG_K_FD = 2,      /* fine-grained (per-partition) peeling             */
     PBNG_K_WING_CD = 3, /* coarse-grained wing batch updates                */
     PBNG_K_DENSE = 4,   /* int8 matrix-core hub tiles                       */
-    PBNG_K_NCLASS = 5
+    PBNG_K_TIP_HRANGE = 5, /* coarse-grained tip peel: the (vertex, key
+                              range) LDS hash kernel alone                  */
+    PBNG_K_NCLASS = 6
 };
 
 typedef struct {

@@ -1737,8 +1737,16 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
                     hipLaunchKernelGGL(k_tip_peel_dense, dim3(std::min<i64>(slots, nF)), dim3(256), 0, s, pd, 3);
                 hipLaunchKernelGGL(k_range_split, dim3(1), dim3(1024), 0, s, (const i32 *)pt.items, (const u32 *)ctl->nbin, 2,
                                    (const u64 *)wi, hoff, htotal);
-                hipLaunchKernelGGL(k_tip_peel_hrange<H_LOGCAP>, dim3(std::min<i64>(slots, (i64)nF * H_RANGE_MAX)), dim3(512), 0,
-                                   s, pt, 2, (const u32 *)hoff, (const u32 *)htotal);
+                c.kend(PBNG_K_TIP_PEEL);
+                {
+                    PeelArgs ph = pt;
+                    ph.kc = c.kctr + PBNG_K_TIP_HRANGE;
+                    c.kbegin(PBNG_K_TIP_HRANGE);
+                    hipLaunchKernelGGL(k_tip_peel_hrange<H_LOGCAP>, dim3(std::min<i64>(slots, (i64)nF * H_RANGE_MAX)), dim3(512),
+                                       0, s, ph, 2, (const u32 *)hoff, (const u32 *)htotal);
+                    c.kend(PBNG_K_TIP_HRANGE);
+                }
+                c.kbegin(PBNG_K_TIP_PEEL);
                 hipLaunchKernelGGL((k_tip_peel_hash<256, 13>), dim3(std::min<i64>((i64)c.num_cu * 2, nF)), dim3(256), 0, s, pm, 1);
                 hipLaunchKernelGGL((k_tip_peel_hash<64, 10>), dim3(std::min<i64>((i64)c.num_cu * 16, nF)), dim3(64), 0, s, pa, 0);
                 c.kend(PBNG_K_TIP_PEEL);
