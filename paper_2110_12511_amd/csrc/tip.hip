@@ -1215,30 +1215,49 @@ struct FdArgs {
     u32 *lcnt;
     i32 *ltouch;
     i32 *lbatch;
+    i32 *lheavy;
     i64 maxni;
     u64 *wedges;
     KCounters *kc;
 };
 
-// One workgroup peels one partition at a time with sequential bottom-up
-// peeling on its induced subgraph: take every alive vertex at the current
-// minimum support k (peeling a whole level at once is exact because the
-// max(k, .) clamps of one level commute), then for each of them walk its
-// wedges inside the partition and lower the supports of the other alive
-// vertices to max(k, support - C(c, 2)).
-__global__ __launch_bounds__(256) void k_tip_fd(FdArgs a) {
-    constexpr int BLOCK = 256;
+// One workgroup peels one partition at a time with bottom-up peeling on its
+// induced subgraph, a whole level at once: take every alive vertex at the
+// current minimum support k, lower every other alive vertex's support by
+// C(c, 2) for each of them (c = common neighbours inside the partition), then
+// clamp to k.  The clamps of one level commute, max(k, max(k, s - a) - b) =
+// max(k, s - a - b), so the decrements are applied in any order as signed
+// atomic subtractions and the clamp is taken once at the end of the level.
+// Batch vertices with at most FD_WAVE_W wedges inside the partition are
+// counted one per wave in a private LDS hash; the rest one at a time by the
+// whole workgroup with the partition-wide counters.
+constexpr int FD_BLOCK = 512;
+constexpr int FD_WAVE_LOG = 9;                        // per-wave hash slots (log2)
+constexpr int FD_WAVE_W = (1 << FD_WAVE_LOG) * 5 / 8;  // wedges a wave hash takes
+
+__global__ __launch_bounds__(FD_BLOCK) void k_tip_fd(FdArgs a) {
+    constexpr int BLOCK = FD_BLOCK;
+    constexpr int NW = BLOCK / WAVE;
+    constexpr int HCAP = 1 << FD_WAVE_LOG;
     __shared__ i32 s_pre[BLOCK];
     __shared__ i64 s_moff[BLOCK];
-    __shared__ i32 s_wave[BLOCK / WAVE];
-    __shared__ u64 s_red[BLOCK / WAVE];
+    __shared__ i32 s_wave[NW];
+    __shared__ u64 s_red[NW];
     __shared__ i32 s_item;
-    __shared__ u32 s_cnt[2];
-    u64 *lsup = a.lsup + blockIdx.x * a.maxni;
+    __shared__ u32 s_cnt[3];
+    __shared__ i32 hkeys[NW][HCAP];
+    __shared__ u32 hvals[NW][HCAP];
+    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+    i64 *lsup = reinterpret_cast<i64 *>(a.lsup) + blockIdx.x * a.maxni;
     unsigned char *lst = a.lst + blockIdx.x * a.maxni;
     u32 *lcnt = a.lcnt + blockIdx.x * a.maxni;
     i32 *ltouch = a.ltouch + blockIdx.x * a.maxni;
     i32 *lbatch = a.lbatch + blockIdx.x * a.maxni;
+    i32 *lheavy = a.lheavy + blockIdx.x * a.maxni;
+    for (int i = lane; i < HCAP; i += WAVE) {
+        hkeys[wid][i] = -1;
+        hvals[wid][i] = 0;
+    }
     u64 wedges = 0;
     for (;;) {
         if (threadIdx.x == 0) s_item = (i32)atomicAdd(a.head, 1u);
@@ -1250,7 +1269,7 @@ __global__ __launch_bounds__(256) void k_tip_fd(FdArgs a) {
         const i64 base = a.poff[pid];
         const i32 ni = (i32)(a.poff[pid + 1] - base);
         for (i32 k = threadIdx.x; k < ni; k += BLOCK) {
-            st_coherent(&lsup[k], a.init[a.xs[base + k]]);
+            st_coherent(&lsup[k], (i64)a.init[a.xs[base + k]]);
             st_coherent(&lst[k], (unsigned char)1);
             st_coherent(&lcnt[k], 0u);
         }
@@ -1260,15 +1279,15 @@ __global__ __launch_bounds__(256) void k_tip_fd(FdArgs a) {
             u64 mn = ~0ull;
             for (i32 k = threadIdx.x; k < ni; k += BLOCK)
                 if (ld_coherent(&lst[k]) == 1) {
-                    u64 s = ld_coherent(&lsup[k]);
-                    mn = s < mn ? s : mn;
+                    const u64 v = (u64)ld_coherent(&lsup[k]);
+                    mn = v < mn ? v : mn;
                 }
             const u64 kmin = block_min_u64<BLOCK>(mn, s_red);
-            if (threadIdx.x == 0) s_cnt[0] = 0;
+            if (threadIdx.x == 0) s_cnt[0] = s_cnt[2] = 0;
             __syncthreads();
             for (i32 k = threadIdx.x; k < ni; k += BLOCK) {
-                if (ld_coherent(&lst[k]) == 1 && ld_coherent(&lsup[k]) == kmin) {
-                    u32 p = atomicAdd(&s_cnt[0], 1u);
+                if (ld_coherent(&lst[k]) == 1 && (u64)ld_coherent(&lsup[k]) == kmin) {
+                    const u32 p = atomicAdd(&s_cnt[0], 1u);
                     st_coherent(&lbatch[p], k);
                     st_coherent(&lst[k], (unsigned char)2);
                     a.theta[a.xs[base + k]] = kmin;
@@ -1276,14 +1295,84 @@ __global__ __launch_bounds__(256) void k_tip_fd(FdArgs a) {
             }
             __syncthreads();
             const i32 nb = (i32)s_cnt[0];
-            __syncthreads();
-            for (i32 b = 0; b < nb; ++b) {
+            // wave per batch vertex: count c(x, x') in the wave's hash
+            for (i32 b = wid; b < nb; b += NW) {
                 const i32 x = a.xs[base + ld_coherent(&lbatch[b])];
+                const i64 jb = a.xrow[x], je = a.xrow[x + 1];
+                i64 tw = 0;
+                for (i64 j = jb + lane; j < je; j += WAVE) tw += a.flen[j];
+                for (int d = WAVE / 2; d > 0; d >>= 1) tw += __shfl_xor(tw, d, WAVE);
+                if (tw > FD_WAVE_W) {
+                    if (lane == 0) lheavy[atomicAdd(&s_cnt[2], 1u)] = x;
+                    continue;
+                }
+                if (tw == 0) continue;
+                for (i64 cb = jb; cb < je; cb += WAVE) {
+                    const i64 j = cb + lane;
+                    i32 pl = 0;
+                    i64 moff = 0;
+                    if (j < je) {
+                        pl = a.flen[j];
+                        moff = a.flo[j];
+                    }
+                    i32 incl = pl;
+                    for (int d = 1; d < WAVE; d <<= 1) {
+                        const i32 y = __shfl_up(incl, d, WAVE);
+                        if (lane >= d) incl += y;
+                    }
+                    const i32 tot = __shfl(incl, WAVE - 1, WAVE);
+                    // lanes walk the wedges of the chunk; the owning entry of
+                    // wedge k is the first lane whose inclusive prefix exceeds k
+                    s_pre[threadIdx.x] = incl;
+                    s_moff[threadIdx.x] = moff;
+                    __builtin_amdgcn_wave_barrier();
+                    for (i32 k = lane; k < tot; k += WAVE) {
+                        int lo = 0, hi = WAVE - 1;
+                        while (lo < hi) {
+                            const int md = (lo + hi) >> 1;
+                            if (s_pre[wid * WAVE + md] > k) hi = md; else lo = md + 1;
+                        }
+                        const i32 before = lo ? s_pre[wid * WAVE + lo - 1] : 0;
+                        const i32 xp = a.yps[s_moff[wid * WAVE + lo] + (k - before)];
+                        if (xp == x) continue;
+                        ++wedges;
+                        const i32 kp = a.loc[xp];
+                        if (ld_coherent(&lst[kp]) != 1) continue;
+                        u32 h = hash32((u32)kp) >> (32 - FD_WAVE_LOG);
+                        for (;;) {
+                            const i32 kk = hkeys[wid][h];
+                            if (kk == kp) break;
+                            if (kk == -1) {
+                                const i32 prev = atomicCAS(&hkeys[wid][h], -1, kp);
+                                if (prev == -1 || prev == kp) break;
+                            }
+                            h = (h + 1) & (HCAP - 1);
+                        }
+                        atomicAdd(&hvals[wid][h], 1u);
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                }
+                __builtin_amdgcn_wave_barrier();
+                for (int i = lane; i < HCAP; i += WAVE) {
+                    const i32 kk = hkeys[wid][i];
+                    if (kk == -1) continue;
+                    const u64 cc = hvals[wid][i];
+                    hkeys[wid][i] = -1;
+                    hvals[wid][i] = 0;
+                    if (cc >= 2) atomicAdd((unsigned long long *)&lsup[kk], (unsigned long long)(0ull - cc * (cc - 1) / 2));
+                }
+                __builtin_amdgcn_wave_barrier();
+            }
+            __syncthreads();
+            // vertices with many wedges: the whole workgroup, one at a time
+            const i32 nh = (i32)s_cnt[2];
+            for (i32 b = 0; b < nh; ++b) {
+                const i32 x = ld_coherent(&lheavy[b]);
                 if (threadIdx.x == 0) s_cnt[1] = 0;
                 __syncthreads();
                 const i64 jb = a.xrow[x], je = a.xrow[x + 1];
                 for (i64 cb = jb; cb < je; cb += BLOCK) {
-                    i64 j = cb + threadIdx.x;
+                    const i64 j = cb + threadIdx.x;
                     i32 pl = 0;
                     i64 moff = 0;
                     if (j < je) {
@@ -1291,24 +1380,25 @@ __global__ __launch_bounds__(256) void k_tip_fd(FdArgs a) {
                         moff = a.flo[j];
                     }
                     i32 tot;
-                    i32 incl = block_incl_scan_i32<BLOCK>(pl, s_wave, tot);
+                    const i32 incl = block_incl_scan_i32<BLOCK>(pl, s_wave, tot);
                     s_pre[threadIdx.x] = incl;
                     s_moff[threadIdx.x] = moff;
                     __syncthreads();
+                    const int last = (je - cb < BLOCK ? (int)(je - cb) : BLOCK) - 1;
                     for (i32 k = threadIdx.x; k < tot; k += BLOCK) {
-                        int lo = 0, hi = BLOCK - 1;
+                        int lo = 0, hi = last;
                         while (lo < hi) {
-                            int md = (lo + hi) >> 1;
+                            const int md = (lo + hi) >> 1;
                             if (s_pre[md] > k) hi = md; else lo = md + 1;
                         }
-                        i32 before = lo ? s_pre[lo - 1] : 0;
-                        i32 xp = a.yps[s_moff[lo] + (k - before)];
+                        const i32 before = lo ? s_pre[lo - 1] : 0;
+                        const i32 xp = a.yps[s_moff[lo] + (k - before)];
                         if (xp == x) continue;
                         ++wedges;
-                        i32 kp = a.loc[xp];
+                        const i32 kp = a.loc[xp];
                         if (ld_coherent(&lst[kp]) != 1) continue;
                         if (atomicAdd(&lcnt[kp], 1u) == 0) {
-                            u32 t = atomicAdd(&s_cnt[1], 1u);
+                            const u32 t = atomicAdd(&s_cnt[1], 1u);
                             st_coherent(&ltouch[t], kp);
                         }
                     }
@@ -1316,18 +1406,22 @@ __global__ __launch_bounds__(256) void k_tip_fd(FdArgs a) {
                 }
                 const u32 nt = s_cnt[1];
                 for (u32 t = threadIdx.x; t < nt; t += BLOCK) {
-                    i32 kp = ld_coherent(&ltouch[t]);
-                    u64 cc = atomicExch(&lcnt[kp], 0u);
-                    if (cc >= 2) {
-                        u64 d = cc * (cc - 1) / 2;
-                        u64 s = ld_coherent(&lsup[kp]);
-                        u64 ns = s > d ? s - d : 0;
-                        st_coherent(&lsup[kp], ns < kmin ? kmin : ns);
-                    }
+                    const i32 kp = ld_coherent(&ltouch[t]);
+                    const u64 cc = atomicExch(&lcnt[kp], 0u);
+                    if (cc >= 2) atomicAdd((unsigned long long *)&lsup[kp], (unsigned long long)(0ull - cc * (cc - 1) / 2));
                 }
                 __syncthreads();
             }
-            for (i32 b = threadIdx.x; b < nb; b += BLOCK) st_coherent(&lst[ld_coherent(&lbatch[b])], (unsigned char)0);
+            // clamp at the level and retire the batch
+            for (i32 k = threadIdx.x; k < ni; k += BLOCK) {
+                const unsigned char st = ld_coherent(&lst[k]);
+                if (st == 2) {
+                    st_coherent(&lst[k], (unsigned char)0);
+                } else if (st == 1) {
+                    const i64 v = ld_coherent(&lsup[k]);
+                    if (v < (i64)kmin) st_coherent(&lsup[k], (i64)kmin);
+                }
+            }
             remaining -= nb;
             __syncthreads();
         }
@@ -1876,11 +1970,12 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
     fa.lcnt = c.alloc<u32>((i64)fdblocks * maxni);
     fa.ltouch = c.alloc<i32>((i64)fdblocks * maxni);
     fa.lbatch = c.alloc<i32>((i64)fdblocks * maxni);
+    fa.lheavy = c.alloc<i32>((i64)fdblocks * maxni);
     fa.wedges = c.alloc<u64>(1);
     fa.kc = c.kctr + PBNG_K_FD;
     PBNG_HIP(hipMemsetAsync(fa.wedges, 0, sizeof(u64), s));
     c.kbegin(PBNG_K_FD);
-    hipLaunchKernelGGL(k_tip_fd, dim3(fdblocks), dim3(256), 0, s, fa);
+    hipLaunchKernelGGL(k_tip_fd, dim3(fdblocks), dim3(FD_BLOCK), 0, s, fa);
     c.kend(PBNG_K_FD);
     PBNG_LAUNCH_CHECK();
     c.stats.wedges_fd = read_scalar<u64>(c, fa.wedges);
