@@ -159,6 +159,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="tip_cl_1m_200k_20m", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-plain bound comparison")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for the CPU baseline")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -235,6 +236,29 @@ def main():
     work = [{k: s[k] for k in ("wedges", "wedges_count", "wedges_cd", "wedges_fd", "rho", "recounts", "partitions",
                                 "P_used", "fd_work_max", "fd_work_sum", "updates", "links", "blooms")} for s in last]
 
+    # learned vs plain range bounds on the same graph and P, outside the timed
+    # steps (tip workloads, when a trained predictor is stored)
+    learned = None
+    if kind == "tip" and not args.no_learned:
+        from paper_2110_12511_amd import predictor
+
+        if predictor.install(ctx):
+            learned = {}
+            for rule_name, rule in (("plain", pb.BOUND_PLAIN), ("learned", pb.BOUND_LEARNED)):
+                per_side = []
+                for side in (pb.SIDE_U, pb.SIDE_V):
+                    t = pb.tip(ctx, dg, side, pb.make_opts(P=P, bound_rule=rule))
+                    torch.cuda.synchronize()
+                    st = ctx.stats()
+                    q = "tip_u" if side == pb.SIDE_U else "tip_v"
+                    rec = golden(graph_cfg, q)
+                    imb = st["fd_work_max"] / max(st["fd_work_sum"] / max(st["partitions"], 1), 1)
+                    per_side.append(dict(side=q, ms_total=round(st["ms_total"], 2), ms_cd=round(st["ms_cd"], 2),
+                                         ms_fd=round(st["ms_fd"], 2), rho=st["rho"], partitions=st["partitions"],
+                                         fd_imbalance=round(imb, 2), rule_used=st["bound_rule_used"],
+                                         exact=(digest(pb.to_numpy_u64(t)) == rec["sha256"]) if rec else None))
+                learned[rule_name] = per_side
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
@@ -260,6 +284,7 @@ def main():
         "work": work,
         "roofline": roofline,
         "copy_kernel": copy,
+        "learned_vs_plain": learned,
         "cpu_baseline": cpu,
         "parity_vs_oracle": parity or None,
     }

@@ -46,8 +46,8 @@ struct TipCtl {
     u32 nF2;        // next active-set size
     u64 wF;         // wedges of the current active set (live lists)
     u64 wedges;     // wedges walked by peeling kernels
-    u32 nbin[4];    // active-set bins: small, medium, tiled, dense
-    u32 next[4];    // work counters
+    u32 nbin[5];    // active-set bins: small, medium, hash ranges, key tiles, pair intersections
+    u32 next[5];    // work counters
     u32 ndirty;     // Y lists to compact
     u32 nyt;        // pull rounds: Y vertices touched by the active set
     u32 nrecv;      // pull rounds: receivers
@@ -67,6 +67,12 @@ constexpr int TILE_LOG = 16;
 constexpr i64 HUGE_W = i64(1) << 18;
 // LDS hash slots of the (vertex, key range) path
 constexpr int H_LOGCAP = 14;
+// active vertices with 2..PAIR_DMAX neighbours whose pairwise list
+// intersections cost less than 1 / PAIR_COST of their wedges take that path
+constexpr i64 PAIR_DMAX = 8;
+constexpr u64 PAIR_COST = 4;
+
+__device__ __forceinline__ int bits_of(u32 v) { return v ? 32 - __clz(v) : 0; }
 
 struct PeelArgs {
     const i64 *xrow;
@@ -599,6 +605,71 @@ __global__ __launch_bounds__(512) void k_tip_peel_hrange(PeelArgs a, int bin, co
     tl.flush(a.kc, a.wedges);
 }
 
+// Active vertices with few neighbours: C(c, 2) for a vertex x' is the number
+// of pairs {y_i, y_j} of x's neighbours whose live lists both hold x', so the
+// decrements come from the pairwise intersections of x's neighbour lists:
+// every element of the shorter list of a pair is searched in the longer one
+// (both sorted by X id) and each hit on an alive vertex lowers its support by
+// one.  The total per vertex equals the wedge-counting path's C(c, 2).  One
+// wave per vertex; a decrement that reaches the bound enqueues the vertex.
+__global__ void k_tip_peel_pairs(PeelArgs a, int bin) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const i64 wave = (blockIdx.x * (i64)blockDim.x + threadIdx.x) / WAVE;
+    const i64 nwaves = (i64)gridDim.x * blockDim.x / WAVE;
+    const u32 n = a.nitems[bin];
+    const i32 *items = a.items;
+    const u64 B = *a.bound;
+    Tally tl;
+    for (i64 it = wave; it < n; it += nwaves) {
+        const i32 x = items[it];
+        const i64 jb = a.xrow[x];
+        const int d = (int)(a.xrow[x + 1] - jb);
+        // neighbour lists in lanes 0..d-1
+        i64 lb = 0;
+        i32 ll = 0;
+        if (lane < d) {
+            const i32 y = a.xadj[jb + lane];
+            lb = a.yrow[y];
+            ll = a.ylen[y];
+        }
+        if (lane == 0) {
+            tl.segments += (u64)d;
+            tl.items += 1;
+        }
+        for (int i = 0; i < d; ++i) {
+            const i64 bi = __shfl(lb, i, WAVE);
+            const i32 li = __shfl(ll, i, WAVE);
+            for (int j = i + 1; j < d; ++j) {
+                const i64 bj = __shfl(lb, j, WAVE);
+                const i32 lj = __shfl(ll, j, WAVE);
+                const bool si = li <= lj;
+                const i64 sb = si ? bi : bj, gb = si ? bj : bi;
+                const i32 sl = si ? li : lj, gl = si ? lj : li;
+                for (i32 k = lane; k < sl; k += WAVE) {
+                    const i32 v = a.yadj[sb + k];
+                    ++tl.wedges;
+                    if (v == x) continue;
+                    // lower bound of v in the longer list
+                    i32 lo = 0, hi = gl;
+                    while (lo < hi) {
+                        const i32 md = (lo + hi) >> 1;
+                        if (a.yadj[gb + md] < v) lo = md + 1; else hi = md;
+                    }
+                    if (lo == gl || a.yadj[gb + lo] != v) continue;
+                    if (a.st[v] != ST_ALIVE) continue;
+                    const u64 old = atomicAdd((unsigned long long *)&a.sup[v], (unsigned long long)(0ull - 1ull));
+                    ++tl.atomics;
+                    if (old == B) {
+                        const u32 p = atomicAdd(a.nnf, 1u);
+                        a.nf[p] = v;
+                    }
+                }
+            }
+        }
+    }
+    tl.flush(a.kc, a.wedges);
+}
+
 // Heavy active vertices, streaming form: every wedge issues one
 // fire-and-forget increment of a per-workgroup HBM counter c[x'] and sets
 // bit x' of a touched bitmap held in LDS (one bit per X vertex).  After the
@@ -965,12 +1036,36 @@ __global__ void k_item_work(const i32 *F, const u32 *nF, const i64 *xrow, const 
         u64 s = 0;
         for (i64 j = jb + lane; j < je; j += WAVE) s += (u64)ylen[xadj[j]];
         for (int dd = WAVE / 2; dd > 0; dd >>= 1) s += __shfl_down(s, dd, WAVE);
+        const i64 d = je - jb;
+        // a vertex with one neighbour shares at most one with anyone: c <= 1,
+        // C(c, 2) = 0, so peeling it updates nothing and it is not walked
+        if (d < 2) s = 0;
+        // few neighbours: cost of the pairwise list intersections (each
+        // element of the shorter list searched in the longer one)
+        u64 pc = ~0ull;
+        if (d >= 2 && d <= PAIR_DMAX) {
+            const u32 l = lane < d ? (u32)ylen[xadj[jb + lane]] : 0u;
+            u64 acc = 0;
+            for (int i = 0; i < (int)d; ++i) {
+                const u32 li = __shfl(l, i, WAVE);
+                if (lane > i && lane < d) {
+                    const u32 mn = li < l ? li : l, mx = li < l ? l : li;
+                    acc += (u64)mn * (u64)(bits_of(mx) + 1);
+                }
+            }
+            for (int dd = WAVE / 2; dd > 0; dd >>= 1) acc += __shfl_down(acc, dd, WAVE);
+            pc = acc;
+        }
         if (lane == 0) {
-            wi[x] = s;
-            atomicAdd((unsigned long long *)wsum, (unsigned long long)s);
+            const bool pairs = s >= 2 && pc != ~0ull && PAIR_COST * pc < s;
+            // the work estimate is what the chosen method walks
+            const u64 sw = pairs ? pc : s;
+            wi[x] = sw;
+            atomicAdd((unsigned long long *)wsum, (unsigned long long)sw);
             if (s >= 2) {
                 int b;
-                if (s <= (u64)T_SMALL_W) b = 0;
+                if (pairs) b = 4;
+                else if (s <= (u64)T_SMALL_W) b = 0;
                 else if (s <= (u64)T_MEDIUM_W) b = 1;
                 else if (s <= huge_w) b = 2;
                 else b = 3;
@@ -1096,7 +1191,7 @@ __global__ void k_set_bound(TipCtl *ctl, int last) {
     ctl->nF2 = 0;
     ctl->wF = 0;
     ctl->est_final = 0;
-    for (int b = 0; b < 4; ++b) ctl->nbin[b] = ctl->next[b] = 0;
+    for (int b = 0; b < 5; ++b) ctl->nbin[b] = ctl->next[b] = 0;
     ctl->nyt = ctl->nrecv = 0;
 }
 
@@ -1105,13 +1200,13 @@ __global__ void k_next_round(TipCtl *ctl) {
     ctl->nF = ctl->nF2;
     ctl->nF2 = 0;
     ctl->wF = 0;
-    for (int b = 0; b < 4; ++b) ctl->nbin[b] = ctl->next[b] = 0;
+    for (int b = 0; b < 5; ++b) ctl->nbin[b] = ctl->next[b] = 0;
     ctl->ndirty = 0;
     ctl->nyt = ctl->nrecv = 0;
 }
 
 __global__ void k_clear_bins(TipCtl *ctl) {
-    for (int b = 0; b < 4; ++b) ctl->nbin[b] = ctl->next[b] = 0;
+    for (int b = 0; b < 5; ++b) ctl->nbin[b] = ctl->next[b] = 0;
 }
 
 __global__ void k_scale(TipCtl *ctl) {
@@ -1568,7 +1663,7 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
     i32 *yadj = c.alloc<i32>(m);
     i32 *F = c.alloc<i32>(nx);
     i32 *F2 = c.alloc<i32>(nx);
-    i32 *bins = c.alloc<i32>(4 * nx);
+    i32 *bins = c.alloc<i32>(5 * nx);
     u64 *wi = c.alloc<u64>(nx);
     TipCtl *ctl = c.alloc<TipCtl>(1);
     PBNG_HIP(hipMemsetAsync(st, 0, nx, s));
@@ -1841,6 +1936,12 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
                     c.kend(PBNG_K_TIP_HRANGE);
                 }
                 c.kbegin(PBNG_K_TIP_PEEL);
+                {
+                    PeelArgs pp = pa;
+                    pp.items = bins + 4 * nx;
+                    hipLaunchKernelGGL(k_tip_peel_pairs, dim3(std::min<i64>((i64)c.num_cu * 8, ((i64)nF + 3) / 4)), dim3(256), 0,
+                                       s, pp, 4);
+                }
                 hipLaunchKernelGGL((k_tip_peel_hash<256, 13>), dim3(std::min<i64>((i64)c.num_cu * 2, nF)), dim3(256), 0, s, pm, 1);
                 hipLaunchKernelGGL((k_tip_peel_hash<64, 10>), dim3(std::min<i64>((i64)c.num_cu * 16, nF)), dim3(64), 0, s, pa, 0);
                 c.kend(PBNG_K_TIP_PEEL);
