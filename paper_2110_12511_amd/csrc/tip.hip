@@ -107,39 +107,44 @@ struct ItemSmem {
 };
 
 // Every wedge x -> y -> x' of an active x over the live Y lists is counted
-// per x'; then every alive x' with c >= 2 loses C(c, 2) of its support, and
-// a support that crosses below the bound puts x' in the next active set
-// (exactly once: supports only decrease).  Keys that are not alive (other
-// active vertices) are dropped in that epilogue, once per key.
-// Support updates of a batch of NB (key, count) pairs: the state loads and
-// the atomics of the batch are issued back to back so their latencies
-// overlap.  Keys < 0 or counts < 2 are skipped; so are vertices that are not
-// alive (peeled earlier or active this round).  A vertex whose support
-// crosses below the bound joins the next active set.
+// per x'; then every alive x' with c >= 2 loses C(c, 2) of its support; after
+// the round the alive vertices whose support fell below the bound form the
+// next active set.  Keys that are not alive (other active vertices) are
+// dropped in that epilogue, once per key.
+// Support updates of a batch of NB (key, count) pairs.  Keys < 0 or counts
+// < 2 are skipped; so are vertices that are not alive (peeled earlier or
+// active this round).  The subtractions are fire-and-forget atomics (no
+// returned value to wait for): the next active set is found after the round
+// by k_sweep_frontier, as every alive vertex whose support fell below the
+// bound, the same set the crossings would give.
 template <int NB>
 __device__ __forceinline__ void apply_updates(const PeelArgs &a, u64 B, const i32 (&key)[NB], const u32 (&cnt)[NB],
                                               Tally &t) {
+    (void)B;
     bool ok[NB];
 #pragma unroll
     for (int q = 0; q < NB; ++q) ok[q] = key[q] >= 0 && cnt[q] >= 2;
 #pragma unroll
     for (int q = 0; q < NB; ++q)
         if (ok[q]) ok[q] = a.st[key[q]] == ST_ALIVE;
-    u64 old[NB], dd[NB];
-#pragma unroll
-    for (int q = 0; q < NB; ++q) {
-        dd[q] = (u64)cnt[q] * (u64)(cnt[q] - 1) / 2;
-        old[q] = 0;
-        if (ok[q]) old[q] = atomicAdd((unsigned long long *)&a.sup[key[q]], (unsigned long long)(0ull - dd[q]));
-    }
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
         if (!ok[q]) continue;
+        const u64 dd = (u64)cnt[q] * (u64)(cnt[q] - 1) / 2;
+        atomicAdd((unsigned long long *)&a.sup[key[q]], (unsigned long long)(0ull - dd));
         ++t.atomics;
-        if (old[q] >= B && old[q] - dd[q] < B) {
-            const u32 p = atomicAdd(a.nnf, 1u);
-            a.nf[p] = key[q];
-        }
+    }
+}
+
+// next active set of a push round: alive vertices below the bound
+__global__ void k_sweep_frontier(const unsigned char *st, const u64 *sup, const TipCtl *ctl, i64 nx, i32 *nf, u32 *nnf) {
+    const u64 B = ctl->bound;
+    const i64 stride = (i64)gridDim.x * blockDim.x;
+    const i64 nn = (nx + WAVE - 1) / WAVE * WAVE;
+    for (i64 x = blockIdx.x * (i64)blockDim.x + threadIdx.x; x < nn; x += stride) {
+        const bool take = x < nx && st[x] == ST_ALIVE && sup[x] < B;
+        const u32 p = wave_append(nnf, take);
+        if (take) nf[p] = (i32)x;
     }
 }
 
@@ -611,14 +616,13 @@ __global__ __launch_bounds__(512) void k_tip_peel_hrange(PeelArgs a, int bin, co
 // every element of the shorter list of a pair is searched in the longer one
 // (both sorted by X id) and each hit on an alive vertex lowers its support by
 // one.  The total per vertex equals the wedge-counting path's C(c, 2).  One
-// wave per vertex; a decrement that reaches the bound enqueues the vertex.
+// wave per vertex.
 __global__ void k_tip_peel_pairs(PeelArgs a, int bin) {
     const int lane = threadIdx.x & (WAVE - 1);
     const i64 wave = (blockIdx.x * (i64)blockDim.x + threadIdx.x) / WAVE;
     const i64 nwaves = (i64)gridDim.x * blockDim.x / WAVE;
     const u32 n = a.nitems[bin];
     const i32 *items = a.items;
-    const u64 B = *a.bound;
     Tally tl;
     for (i64 it = wave; it < n; it += nwaves) {
         const i32 x = items[it];
@@ -657,12 +661,8 @@ __global__ void k_tip_peel_pairs(PeelArgs a, int bin) {
                     }
                     if (lo == gl || a.yadj[gb + lo] != v) continue;
                     if (a.st[v] != ST_ALIVE) continue;
-                    const u64 old = atomicAdd((unsigned long long *)&a.sup[v], (unsigned long long)(0ull - 1ull));
+                    atomicAdd((unsigned long long *)&a.sup[v], (unsigned long long)(0ull - 1ull));
                     ++tl.atomics;
-                    if (old == B) {
-                        const u32 p = atomicAdd(a.nnf, 1u);
-                        a.nf[p] = v;
-                    }
                 }
             }
         }
@@ -749,12 +749,8 @@ __global__ __launch_bounds__(512) void k_tip_peel_bits(PeelArgs a, int bin) {
                 const u64 cc = __hip_atomic_exchange(&cnt[xp], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 if (cc < 2 || a.st[xp] != ST_ALIVE) continue;
                 const u64 dd = cc * (cc - 1) / 2;
-                const u64 old = atomicAdd((unsigned long long *)&a.sup[xp], (unsigned long long)(0ull - dd));
+                atomicAdd((unsigned long long *)&a.sup[xp], (unsigned long long)(0ull - dd));
                 ++tl.atomics;
-                if (old >= B && old - dd < B) {
-                    u32 p = atomicAdd(a.nnf, 1u);
-                    a.nf[p] = xp;
-                }
             }
         }
         __syncthreads();
@@ -1945,6 +1941,9 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
                 hipLaunchKernelGGL((k_tip_peel_hash<256, 13>), dim3(std::min<i64>((i64)c.num_cu * 2, nF)), dim3(256), 0, s, pm, 1);
                 hipLaunchKernelGGL((k_tip_peel_hash<64, 10>), dim3(std::min<i64>((i64)c.num_cu * 16, nF)), dim3(64), 0, s, pa, 0);
                 c.kend(PBNG_K_TIP_PEEL);
+                PBNG_LAUNCH_CHECK();
+                hipLaunchKernelGGL(k_sweep_frontier, dim3(gx), dim3(256), 0, s, (const unsigned char *)st, (const u64 *)sup,
+                                   (const TipCtl *)ctl, nx, F2, &ctl->nF2);
                 PBNG_LAUNCH_CHECK();
             }
             if (!(batch && hv.wF > wedge_cnt_bound)) {
