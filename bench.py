@@ -34,12 +34,18 @@ HBM_PEAK_GBS = 8000.0
 CLASS_KERNEL = {"tip_hrange": "k_tip_peel_hrange<14>", "fd": "k_tip_fd / k_wing_fd", "dense": "m_gram"}
 
 WORKLOADS = {
-    # name: (graph config, kind, P)
+    # name: (graph config, kind, P); kinds: tip (both sides), tip_u (side U),
+    # wing (all edges), batch (tip of side U and wing of every graph of a list,
+    # one batched call each)
     "tip_cl_1m_200k_20m": ("cl_1m_200k_20m", "tip", 150),
     "tip_cl_500k_100k_5m": ("cl_500k_100k_5m", "tip", 150),
     "wing_cl_500k_100k_5m": ("cl_500k_100k_5m", "wing", 400),
     "tip_er_2k_1k_20k": ("er_2k_1k_20k", "tip", 8),
+    "tip_u_cl_5m_1m_100m": ("cl_5m_1m_100m", "tip_u", 150),
+    "batch_mixed_1024": ("mixed_1024", "batch", 0),
 }
+# batch lists: (number of graphs, smallest and largest edge count)
+BATCHES = {"mixed_1024": (1024, 1e3, 1e5)}
 
 
 def log(*a):
@@ -62,10 +68,15 @@ def run_step(pb, ctx, dg, kind, P, flags):
     """One pass of the hot path; returns (outputs, list of stats dicts)."""
     opts = pb.make_opts(P=P, flags=flags)
     outs, stats = [], []
-    if kind == "tip":
-        for side in (pb.SIDE_U, pb.SIDE_V):
+    if kind in ("tip", "tip_u"):
+        for side in ((pb.SIDE_U, pb.SIDE_V) if kind == "tip" else (pb.SIDE_U,)):
             outs.append(pb.tip(ctx, dg, side, opts))
             stats.append(ctx.stats())
+    elif kind == "batch":
+        outs.append(pb.tip_batch(ctx, dg, pb.SIDE_U, opts))
+        stats.append(ctx.stats())
+        outs.append(pb.wing_batch(ctx, dg, opts))
+        stats.append(ctx.stats())
     else:
         outs.append(pb.wing(ctx, dg, opts))
         stats.append(ctx.stats())
@@ -123,6 +134,20 @@ def cpu_baseline(graph_cfg, kind, budget_s):
     import oracle
     import synth
 
+    if kind == "batch":
+        # the batch's own graphs in order until the budget is spent
+        nb, m_min, m_max = BATCHES[graph_cfg]
+        wedges, dt, k = 0, 0.0, 0
+        while k < nb and dt * 2 < budget_s:
+            g = synth.mixed_graph(k, m_min, m_max)
+            t0 = time.perf_counter()
+            _, st = oracle.tip(g, 0, return_stats=True)
+            dt += time.perf_counter() - t0
+            wedges += 2 * st["wedges"]
+            k += 1
+        return dict(value=wedges / dt if dt > 0 else 0.0, unit="wedges/s", cores=1, kind="oracle",
+                    sample=f"the first {k} graphs of the batch: tip side U by sequential bottom-up peeling, "
+                           f"{wedges} wedges in {dt:.2f} s", seconds=round(dt, 2))
     c = dict(synth.CONFIGS[graph_cfg])
     gen = c.pop("kind")
     scale = 64
@@ -135,7 +160,7 @@ def cpu_baseline(graph_cfg, kind, budget_s):
             kw["cap"] = max(8, c["cap"] // scale)
         g = synth.er(**kw) if gen == "er" else synth.chung_lu(**kw)
         t0 = time.perf_counter()
-        if kind == "tip":
+        if kind in ("tip", "tip_u"):
             _, st = oracle.tip(g, 0, return_stats=True)
             # counting walks the same wedges as peeling without graph updates
             wedges = 2 * st["wedges"]
@@ -174,10 +199,22 @@ def main():
 
     graph_cfg, kind, P = WORKLOADS[args.workload]
     log(f"[bench] generating {graph_cfg}")
-    g = synth.config_graph(graph_cfg)
-    log(f"[bench] graph {g.name}: m={g.m}")
+    if kind == "batch":
+        nb, m_min, m_max = BATCHES[graph_cfg]
+        graphs = [synth.mixed_graph(i, m_min, m_max) for i in range(nb)]
+        g = synth.Graph(n_u=sum(x.n_u for x in graphs), n_v=sum(x.n_v for x in graphs),
+                        row_ptr=np.zeros(1, np.int64), col_idx=np.zeros(0, np.int32),
+                        name=f"{nb} graphs, m log-uniform in [{m_min:.0e}, {m_max:.0e}], half ER half CL")
+        g_m = sum(x.m for x in graphs)
+    else:
+        g = synth.config_graph(graph_cfg, log=log)
+        g_m = g.m
+    log(f"[bench] graph {g.name}: m={g_m}")
     ctx = pb.Context()
-    dg = pb.DeviceGraph.from_graph(g)
+    if kind == "batch":
+        dg = [pb.DeviceGraph.from_graph(x) for x in graphs]
+    else:
+        dg = pb.DeviceGraph.from_graph(g)
     torch.cuda.synchronize()
     copy = copy_probe(torch)
     log(f"[bench] copy kernel: {copy['gbs']} GB/s")
@@ -224,7 +261,7 @@ def main():
 
     # parity evidence against stored oracle results (when present)
     parity = {}
-    qnames = ["tip_u", "tip_v"] if kind == "tip" else ["wing"]
+    qnames = {"tip": ["tip_u", "tip_v"], "tip_u": ["tip_u"], "wing": ["wing"]}.get(kind, [])
     for q, t in zip(qnames, outs):
         rec = golden(graph_cfg, q)
         if rec is not None:
@@ -239,14 +276,14 @@ def main():
     # learned vs plain range bounds on the same graph and P, outside the timed
     # steps (tip workloads, when a trained predictor is stored)
     learned = None
-    if kind == "tip" and not args.no_learned:
+    if kind in ("tip", "tip_u") and not args.no_learned:
         from paper_2110_12511_amd import predictor
 
         if predictor.install(ctx):
             learned = {}
             for rule_name, rule in (("plain", pb.BOUND_PLAIN), ("learned", pb.BOUND_LEARNED)):
                 per_side = []
-                for side in (pb.SIDE_U, pb.SIDE_V):
+                for side in ((pb.SIDE_U, pb.SIDE_V) if kind == "tip" else (pb.SIDE_U,)):
                     t = pb.tip(ctx, dg, side, pb.make_opts(P=P, bound_rule=rule))
                     torch.cuda.synchronize()
                     st = ctx.stats()
@@ -277,8 +314,10 @@ def main():
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": f"{kind} decomposition ({'both sides' if kind == 'tip' else 'all edges'}) of {g.name}",
-                   "graph": graph_cfg, "P": P, "bound_rule": "plain", "m": g.m, "n_u": g.n_u, "n_v": g.n_v},
+        "config": {"workload": {"tip": "tip decomposition (both sides)", "tip_u": "tip decomposition (side U)",
+                                "wing": "wing decomposition (all edges)",
+                                "batch": "batched tip (side U) and wing decompositions"}[kind] + f" of {g.name}",
+                   "graph": graph_cfg, "P": P, "bound_rule": "plain", "m": g_m, "n_u": g.n_u, "n_v": g.n_v},
         "decomposition_ms": round(min(step_ms), 2),
         "phases_ms": phases,
         "work": work,

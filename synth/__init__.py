@@ -20,6 +20,9 @@ Generators
     vertices are kept.
 ``complete(a, b)``
     K_{a,b}.
+``mixed_graph(gi, m_min, m_max)``
+    Graph gi of a family of uneven sizes (half Erdos-Renyi, half Chung-Lu)
+    for batched calls.
 
 All randomness comes from numpy's counter-based Philox generator, keyed by
 the seed, so a (generator, parameters, seed) triple names one graph.
@@ -32,6 +35,7 @@ from .bipartite import (  # noqa: F401
     from_edges,
     disjoint_union,
     random_small,
+    mixed_graph,
     config_graph,
     CONFIGS,
 )

@@ -105,8 +105,9 @@ def _capped_weights(n: int, m: int, gamma: float, cap: float) -> np.ndarray:
     return np.minimum(hi * r, cap)
 
 
-def chung_lu(n_u: int, n_v: int, m: int, gamma: float, cap: float, seed: int) -> Graph:
-    """Chung-Lu bipartite graph with power-law expected degrees on both sides."""
+def chung_lu(n_u: int, n_v: int, m: int, gamma: float, cap: float, seed: int, log=None) -> Graph:
+    """Chung-Lu bipartite graph with power-law expected degrees on both sides.
+    ``log`` (optional) receives a progress line after every draw round."""
     rng = _rng(seed)
     wu = _capped_weights(n_u, m, gamma, min(cap, n_v))
     wv = _capped_weights(n_v, m, gamma, min(cap, n_u))
@@ -125,6 +126,8 @@ def chung_lu(n_u: int, n_v: int, m: int, gamma: float, cap: float, seed: int) ->
         np.minimum(xv, n_v - 1, out=xv)
         draws.append(pu[xu] * n_v + pv[xv])
         keys = _first_distinct(draws, m)
+        if log:
+            log(f"[synth] CL({n_u},{n_v},{m}): draw round {_ + 1} done")
         if keys is not None:
             return _from_keys(keys, n_u, n_v, f"CL({n_u},{n_v},{m},g={gamma},cap={cap},seed={seed})")
         # keep the distinct draws only, to bound memory
@@ -171,9 +174,21 @@ CONFIGS = {
 }
 
 
-def config_graph(name: str) -> Graph:
+def config_graph(name: str, log=None) -> Graph:
     c = dict(CONFIGS[name])
     kind = c.pop("kind")
     if kind == "er":
         return er(**c)
-    return chung_lu(**c)
+    return chung_lu(**c, log=log)
+
+
+def mixed_graph(gi: int, m_min: float = 1e3, m_max: float = 1e6) -> Graph:
+    """Graph gi of a family of uneven sizes for batched calls: m log-uniform in
+    [m_min, m_max]; even gi Erdos-Renyi with |U| = m/10, |V| = m/20; odd gi
+    Chung-Lu with exponent uniform in [2.0, 2.6], |U| = m/10, |V| = m/50,
+    degree cap 50000.  Seeds 50000 + gi."""
+    rng = np.random.default_rng(50000 + gi)
+    m = int(round(np.exp(rng.uniform(np.log(m_min), np.log(m_max)))))
+    if gi % 2 == 0:
+        return er(max(m // 10, 2), max(m // 20, 2), m, seed=50000 + gi)
+    return chung_lu(max(m // 10, 2), max(m // 50, 2), m, float(rng.uniform(2.0, 2.6)), 50000, seed=50000 + gi)

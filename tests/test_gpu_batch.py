@@ -70,19 +70,8 @@ def test_batch_rejects_bad_entry(ctx):
     assert e.value.code == -2
 
 
-def mixed_graph(gi):
-    """Graph gi of a family of uneven sizes: m log-uniform in [1e3, 1e5]; even
-    gi Erdos-Renyi (|U| = m/10, |V| = m/20), odd gi Chung-Lu (exponent in
-    [2.0, 2.6], |U| = m/10, |V| = m/50, cap 50000)."""
-    rng = np.random.default_rng(50000 + gi)
-    m = int(round(np.exp(rng.uniform(np.log(1e3), np.log(1e5)))))
-    if gi % 2 == 0:
-        return synth.er(max(m // 10, 2), max(m // 20, 2), m, seed=50000 + gi)
-    return synth.chung_lu(max(m // 10, 2), max(m // 50, 2), m, float(rng.uniform(2.0, 2.6)), 50000, seed=50000 + gi)
-
-
 def test_uneven_batch_matches_single_calls(ctx):
-    gs = [mixed_graph(i) for i in range(96)]
+    gs = [synth.mixed_graph(i, 1e3, 1e5) for i in range(96)]
     dgs = [pb.DeviceGraph.from_graph(g) for g in gs]
     res = pb.tip_batch(ctx, dgs, 0)
     st = ctx.stats()
