@@ -1707,14 +1707,14 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
     // LDS key tiles for heavy active vertices (one 512-lane workgroup per CU)
     const i32 ntiles = (i32)((nx + (i64(1) << TILE_LOG) - 1) >> TILE_LOG);
     const int tslots = c.num_cu;
-    // Active vertices above HUGE_W wedges use LDS key tiles while the X side
-    // has at most 2^20 vertices (16 tiles); streaming into HBM counters with
-    // an LDS touched bitmap is the alternative (PBNG_HEAVY=b) while one bit per
-    // X vertex fits in LDS; beyond that, HBM counters with a touched list.
+    // Active vertices above HUGE_W wedges use LDS key tiles (one work item per
+    // vertex and 2^16-key tile); streaming into HBM counters with an LDS
+    // touched bitmap is the alternative (PBNG_HEAVY=b) while one bit per X
+    // vertex fits in LDS.  Item indices (vertices x tiles) must fit 32 bits.
     constexpr int BITS_NBW = 1 << 15;
     const char *heavy_env = getenv("PBNG_HEAVY");
     const bool huge_bits = heavy_env && heavy_env[0] == 'b' && nx <= (i64)BITS_NBW * 32;
-    const bool huge_tiled = !huge_bits && nx <= (i64(1) << 20);
+    const bool huge_tiled = !huge_bits && (u64)nx * (u64)ntiles < (u64(1) << 32);
     const u64 huge_w = o.tile_w == 0 ? (u64)HUGE_W : (o.tile_w < 0 ? ~0ull : (u64)o.tile_w);
     u32 *hoff = c.alloc<u32>(nx + 1);
     u32 *htotal = c.alloc<u32>(1);
