@@ -387,6 +387,210 @@ __global__ __launch_bounds__(256) void k_count_dense(CountArgs a) {
     tl.flush(a.kc, a.wedges);
 }
 
+// Large starts of the vertex-count modes, by key tiles.  The lasts of start s
+// have smaller labels than s, and the largest starts are the highest-priority
+// (smallest-label) vertices, so the keys [0, s) of a large start are covered
+// by few tiles of CT = 2^15 consecutive labels (one for every start below
+// 2^15).  A work item is one (start, tile) pair: the run of every mid's
+// prefix inside the tile is found by binary search (no search when the tile
+// is the whole key space), the wedge counts go to dense LDS counters (one u32
+// per key, packed (all mids) + 2^16 (hub mids) in the one-side mode) with a
+// touched-word bitmap, and the epilogue and second pass are those of the
+// hash kernels restricted to the tile's lasts.  Tiles split the lasts, so
+// the per-tile contributions of the start, its lasts and its mids add up to
+// the per-start ones.
+constexpr int CT_LOG = 15;
+
+// tiles of every large start and their exclusive prefix (one workgroup)
+__global__ __launch_bounds__(1024) void k_count_tiles(const i32 *starts, u32 nstarts, u32 *off, u32 *total) {
+    __shared__ i32 s_wave[1024 / WAVE];
+    u32 carry = 0;
+    for (u32 base = 0; base < nstarts; base += 1024) {
+        const u32 i = base + threadIdx.x;
+        i32 r = 0;
+        if (i < nstarts) r = (starts[i] + (1 << CT_LOG) - 1) >> CT_LOG;
+        i32 tot;
+        const i32 incl = block_incl_scan_i32<1024>(r, s_wave, tot);
+        if (i < nstarts) off[i] = carry + (u32)(incl - r);
+        carry += (u32)tot;
+    }
+    if (threadIdx.x == 0) {
+        off[nstarts] = carry;
+        *total = carry;
+    }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(512) void k_count_tiled(CountArgs a, const u32 *off, const u32 *total) {
+    constexpr int BLOCK = 512;
+    constexpr int CT = 1 << CT_LOG;
+    constexpr bool XS = (MODE & M_XSIDE) != 0;
+    __shared__ u32 cnt[CT];
+    __shared__ u32 bm[CT / 32];
+    __shared__ i32 s_pre[BLOCK];
+    __shared__ i64 s_moff[BLOCK];
+    __shared__ u64 s_agg[BLOCK];
+    __shared__ i32 s_wave[BLOCK / WAVE];
+    __shared__ u64 s_red[BLOCK / WAVE];
+    __shared__ u32 s_item;
+    for (int i = threadIdx.x; i < CT; i += BLOCK) cnt[i] = 0;
+    for (int i = threadIdx.x; i < CT / 32; i += BLOCK) bm[i] = 0;
+    const u32 n = *total;
+    const u32 ns = a.nstarts;
+    Tally tl;
+    __syncthreads();
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(a.next, 1u);
+        __syncthreads();
+        const u32 item = s_item;
+        __syncthreads();
+        if (item >= n) break;
+        u32 lo = 0, hi = ns - 1;
+        while (lo < hi) {
+            const u32 md = (lo + hi + 1) >> 1;
+            if (off[md] <= item) lo = md; else hi = md - 1;
+        }
+        const i32 s = a.starts[lo];
+        const i32 t = (i32)(item - off[lo]);
+        const i32 r0 = t << CT_LOG;
+        const i32 r1 = r0 + CT < s ? r0 + CT : s;
+        const bool whole = r0 == 0 && r1 == s;
+        const unsigned char sc = XS ? a.lclass[s] : (unsigned char)0;
+        const i64 jb = a.loff[s], je = a.loff[s + 1];
+        if (threadIdx.x == 0 && t == 0) {
+            tl.segments += (u64)(je - jb);
+            tl.items += 1;
+        }
+        // the wedges of one chunk of mids restricted to the tile; fn(seg, jmid, last, pos)
+        auto walk = [&](auto fn, auto chunk_end) {
+            for (i64 cb = jb; cb < je; cb += BLOCK) {
+                const i64 j = cb + threadIdx.x;
+                i32 pl = 0;
+                i64 moff = 0;
+                if (j < je) {
+                    const i32 mid = a.ladj[j];
+                    i32 len = a.lpl[j];
+                    if (a.alive && !a.alive[mid]) len = 0;
+                    const i64 mb = a.loff[mid];
+                    i64 b0 = mb, e0 = mb + len;
+                    if (!whole && len) {
+                        i64 l2 = mb, h2 = e0;
+                        while (l2 < h2) {
+                            const i64 md = (l2 + h2) >> 1;
+                            if (a.ladj[md] < r0) l2 = md + 1; else h2 = md;
+                        }
+                        b0 = l2;
+                        h2 = e0;
+                        while (l2 < h2) {
+                            const i64 md = (l2 + h2) >> 1;
+                            if (a.ladj[md] < r1) l2 = md + 1; else h2 = md;
+                        }
+                        e0 = l2;
+                    }
+                    pl = (i32)(e0 - b0);
+                    moff = b0;
+                }
+                i32 tot;
+                const i32 incl = block_incl_scan_i32<BLOCK>(pl, s_wave, tot);
+                s_pre[threadIdx.x] = incl;
+                s_moff[threadIdx.x] = moff;
+                __syncthreads();
+                const int last_seg = (je - cb < BLOCK ? (int)(je - cb) : BLOCK) - 1;
+                for (i32 k = threadIdx.x; k < tot; k += BLOCK) {
+                    int l = 0, h = last_seg;
+                    while (l < h) {
+                        const int md = (l + h) >> 1;
+                        if (s_pre[md] > k) h = md; else l = md + 1;
+                    }
+                    const i32 before = l ? s_pre[l - 1] : 0;
+                    const i64 pos = s_moff[l] + (k - before);
+                    const i32 last = a.ladj[pos];
+                    if (a.alive && !a.alive[last]) continue;
+                    fn(l, cb + l, last, pos);
+                }
+                __syncthreads();
+                chunk_end(cb);
+                __syncthreads();
+            }
+        };
+        // pass 1: wedge counts per last of the tile
+        walk(
+            [&](int, i64 jmid, i32 last, i64) {
+                u32 inc = 1u;
+                if (XS && sc == LC_Y && a.lclass[a.ladj[jmid]] == LC_XHUB) inc = 0x10001u;
+                const u32 o = (u32)(last - r0);
+                if (atomicAdd(&cnt[o], inc) == 0u) atomicOr(&bm[o >> 5], 1u << (o & 31));
+                ++tl.wedges;
+            },
+            [&](i64) {});
+        const bool ends = !XS || sc != LC_Y;  // start and lasts get C(c, 2)
+        const bool mids = !XS || sc == LC_Y;  // mids get their shares
+        if (ends) {
+            u64 my_start = 0;
+            const i32 nbw = ((r1 - r0) + 31) >> 5;
+            for (i32 bw = threadIdx.x; bw < nbw; bw += BLOCK) {
+                u32 bits = bm[bw];
+                while (bits) {
+                    const i32 o = bw * 32 + (__ffs(bits) - 1);
+                    bits &= bits - 1;
+                    const u64 cc = XS ? (cnt[o] & 0xFFFFu) : cnt[o];
+                    if (cc < 2) continue;
+                    const u64 b = cc * (cc - 1) / 2;
+                    my_start += b;
+                    atomicAdd((unsigned long long *)&a.sup_label[r0 + o], (unsigned long long)b);
+                    ++tl.atomics;
+                }
+            }
+            const u64 tt = block_sum_u64<BLOCK>(my_start, s_red);
+            if (threadIdx.x == 0 && tt) {
+                atomicAdd((unsigned long long *)&a.sup_label[s], (unsigned long long)tt);
+                ++tl.atomics;
+            }
+            __syncthreads();
+        }
+        if (mids) {
+            s_agg[threadIdx.x] = 0;
+            __syncthreads();
+            walk(
+                [&](int seg, i64 jmid, i32 last, i64) {
+                    const u32 v = cnt[last - r0];
+                    u64 share;
+                    if (XS) {
+                        const u64 cc = v & 0xFFFFu;
+                        if (cc < 2) return;
+                        const u64 hub = v >> 16;
+                        share = a.lclass[a.ladj[jmid]] == LC_XHUB ? cc - hub : cc - 1;
+                    } else {
+                        if (v < 2) return;
+                        share = (u64)v - 1;
+                    }
+                    if (share) atomicAdd((unsigned long long *)&s_agg[seg], (unsigned long long)share);
+                },
+                [&](i64 cb) {
+                    const u64 g = s_agg[threadIdx.x];
+                    if (g) {
+                        atomicAdd((unsigned long long *)&a.sup_label[a.ladj[cb + threadIdx.x]], (unsigned long long)g);
+                        ++tl.atomics;
+                        s_agg[threadIdx.x] = 0;
+                    }
+                });
+        }
+        // clear the touched counters
+        const i32 nbw = ((r1 - r0) + 31) >> 5;
+        for (i32 bw = threadIdx.x; bw < nbw; bw += BLOCK) {
+            u32 bits = bm[bw];
+            if (!bits) continue;
+            bm[bw] = 0;
+            while (bits) {
+                cnt[bw * 32 + (__ffs(bits) - 1)] = 0;
+                bits &= bits - 1;
+            }
+        }
+        __syncthreads();
+    }
+    tl.flush(a.kc, a.wedges);
+}
+
 // ------------------------------------------------------------------ binning
 
 constexpr i64 SMALL_W = 512, MEDIUM_W = 4096;
@@ -441,7 +645,8 @@ static void launch_all(Ctx &c, const DevGraph &G, CountArgs a, const Bins &b) {
     PBNG_HIP(hipMemsetAsync(next, 0, 3 * sizeof(u32), c.stream));
     a.kc = c.kctr + PBNG_K_COUNT;
     const int slots = (int)std::min<i64>(b.cnt[2], (i64)c.num_cu);
-    if (b.cnt[2]) {
+    constexpr bool tiled = MODE == M_XSIDE || MODE == M_VERTEX;
+    if (b.cnt[2] && !tiled) {
         a.dcnt = c.alloc<u32>((i64)slots * G.n);
         a.dtouch = c.alloc<i32>((i64)slots * G.n);
         a.dbid = (MODE & M_BE_FILL) ? c.alloc<i32>((i64)slots * G.n) : nullptr;
@@ -455,7 +660,16 @@ static void launch_all(Ctx &c, const DevGraph &G, CountArgs a, const Bins &b) {
         a.starts = b.lists + 2 * G.n;
         a.nstarts = b.cnt[2];
         a.next = next + 2;
-        hipLaunchKernelGGL(k_count_dense<MODE>, dim3(slots), dim3(256), 0, c.stream, a);
+        if constexpr (MODE == M_XSIDE || MODE == M_VERTEX) {
+            u32 *toff = c.alloc<u32>((i64)b.cnt[2] + 1);
+            u32 *ttot = c.alloc<u32>(1);
+            hipLaunchKernelGGL(k_count_tiles, dim3(1), dim3(1024), 0, c.stream, (const i32 *)a.starts, (u32)b.cnt[2], toff,
+                               ttot);
+            hipLaunchKernelGGL(k_count_tiled<MODE>, dim3(c.num_cu), dim3(512), 0, c.stream, a, (const u32 *)toff,
+                               (const u32 *)ttot);
+        } else {
+            hipLaunchKernelGGL(k_count_dense<MODE>, dim3(slots), dim3(256), 0, c.stream, a);
+        }
         PBNG_LAUNCH_CHECK();
     }
     if (b.cnt[1]) {
