@@ -1323,6 +1323,7 @@ struct FdArgs {
 // counted one per wave in a private LDS hash; the rest one at a time by the
 // whole workgroup with the partition-wide counters.
 constexpr int FD_BLOCK = 512;
+constexpr int FD_LDS_NI = 4096;  // partitions this small live in LDS
 constexpr int FD_WAVE_LOG = 9;                        // per-wave hash slots (log2)
 constexpr int FD_WAVE_W = (1 << FD_WAVE_LOG) * 5 / 8;  // wedges a wave hash takes
 
@@ -1336,14 +1337,23 @@ __global__ __launch_bounds__(FD_BLOCK) void k_tip_fd(FdArgs a) {
     __shared__ u64 s_red[NW];
     __shared__ i32 s_item;
     __shared__ u32 s_cnt[3];
-    __shared__ i32 hkeys[NW][HCAP];
-    __shared__ u32 hvals[NW][HCAP];
+    // per-wave hashes (keys, then counts); during the heavy phase the same
+    // words hold dense packed 16-bit counters over the partition's vertices
+    __shared__ u32 hmem[2 * NW * HCAP];
+    i32(*hkeys)[HCAP] = reinterpret_cast<i32(*)[HCAP]>(hmem);
+    u32(*hvals)[HCAP] = reinterpret_cast<u32(*)[HCAP]>(hmem + NW * HCAP);
+    constexpr i32 DENSE_NI = 2 * 2 * NW * HCAP;  // vertices the dense counters cover
+    // a partition of at most FD_LDS_NI vertices keeps its supports, states and
+    // level batch in LDS; larger ones use the workgroup's HBM slices
+    __shared__ i64 s_lsup[FD_LDS_NI];
+    __shared__ unsigned char s_lst[FD_LDS_NI];
+    __shared__ i32 s_lbatch[FD_LDS_NI];
     const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
-    i64 *lsup = reinterpret_cast<i64 *>(a.lsup) + blockIdx.x * a.maxni;
-    unsigned char *lst = a.lst + blockIdx.x * a.maxni;
+    i64 *const g_lsup = reinterpret_cast<i64 *>(a.lsup) + blockIdx.x * a.maxni;
+    unsigned char *const g_lst = a.lst + blockIdx.x * a.maxni;
     u32 *lcnt = a.lcnt + blockIdx.x * a.maxni;
     i32 *ltouch = a.ltouch + blockIdx.x * a.maxni;
-    i32 *lbatch = a.lbatch + blockIdx.x * a.maxni;
+    i32 *const g_lbatch = a.lbatch + blockIdx.x * a.maxni;
     i32 *lheavy = a.lheavy + blockIdx.x * a.maxni;
     for (int i = lane; i < HCAP; i += WAVE) {
         hkeys[wid][i] = -1;
@@ -1359,21 +1369,22 @@ __global__ __launch_bounds__(FD_BLOCK) void k_tip_fd(FdArgs a) {
         const i32 pid = a.queue[qi];
         const i64 base = a.poff[pid];
         const i32 ni = (i32)(a.poff[pid + 1] - base);
+        const bool in_lds = ni <= FD_LDS_NI;
+        i64 *const lsup = in_lds ? s_lsup : g_lsup;
+        unsigned char *const lst = in_lds ? s_lst : g_lst;
+        i32 *const lbatch = in_lds ? s_lbatch : g_lbatch;
+        u64 mn = ~0ull;
         for (i32 k = threadIdx.x; k < ni; k += BLOCK) {
-            st_coherent(&lsup[k], (i64)a.init[a.xs[base + k]]);
+            const u64 v0 = a.init[a.xs[base + k]];
+            st_coherent(&lsup[k], (i64)v0);
             st_coherent(&lst[k], (unsigned char)1);
             st_coherent(&lcnt[k], 0u);
+            mn = v0 < mn ? v0 : mn;
         }
+        u64 kmin = block_min_u64<BLOCK>(mn, s_red);
         __syncthreads();
         i32 remaining = ni;
         while (remaining > 0) {
-            u64 mn = ~0ull;
-            for (i32 k = threadIdx.x; k < ni; k += BLOCK)
-                if (ld_coherent(&lst[k]) == 1) {
-                    const u64 v = (u64)ld_coherent(&lsup[k]);
-                    mn = v < mn ? v : mn;
-                }
-            const u64 kmin = block_min_u64<BLOCK>(mn, s_red);
             if (threadIdx.x == 0) s_cnt[0] = s_cnt[2] = 0;
             __syncthreads();
             for (i32 k = threadIdx.x; k < ni; k += BLOCK) {
@@ -1457,7 +1468,61 @@ __global__ __launch_bounds__(FD_BLOCK) void k_tip_fd(FdArgs a) {
             __syncthreads();
             // vertices with many wedges: the whole workgroup, one at a time
             const i32 nh = (i32)s_cnt[2];
-            for (i32 b = 0; b < nh; ++b) {
+            const bool dense = ni <= DENSE_NI;
+            if (nh > 0 && dense)
+                for (i32 i = threadIdx.x; i < 2 * NW * HCAP; i += BLOCK) hmem[i] = 0;
+            __syncthreads();
+            for (i32 b = 0; dense && b < nh; ++b) {
+                const i32 x = ld_coherent(&lheavy[b]);
+                const i64 jb = a.xrow[x], je = a.xrow[x + 1];
+                for (i64 cb = jb; cb < je; cb += BLOCK) {
+                    const i64 j = cb + threadIdx.x;
+                    i32 pl = 0;
+                    i64 moff = 0;
+                    if (j < je) {
+                        pl = a.flen[j];
+                        moff = a.flo[j];
+                    }
+                    i32 tot;
+                    const i32 incl = block_incl_scan_i32<BLOCK>(pl, s_wave, tot);
+                    s_pre[threadIdx.x] = incl;
+                    s_moff[threadIdx.x] = moff;
+                    __syncthreads();
+                    const int last = (je - cb < BLOCK ? (int)(je - cb) : BLOCK) - 1;
+                    for (i32 k = threadIdx.x; k < tot; k += BLOCK) {
+                        int lo = 0, hi = last;
+                        while (lo < hi) {
+                            const int md = (lo + hi) >> 1;
+                            if (s_pre[md] > k) hi = md; else lo = md + 1;
+                        }
+                        const i32 before = lo ? s_pre[lo - 1] : 0;
+                        const i32 xp = a.yps[s_moff[lo] + (k - before)];
+                        if (xp == x) continue;
+                        ++wedges;
+                        const i32 kp = a.loc[xp];
+                        if (ld_coherent(&lst[kp]) != 1) continue;
+                        atomicAdd(&hmem[kp >> 1], 1u << ((kp & 1) << 4));
+                    }
+                    __syncthreads();
+                }
+                const i32 nw = (ni + 1) >> 1;
+                for (i32 w = threadIdx.x; w < nw; w += BLOCK) {
+                    const u32 v = hmem[w];
+                    if (!v) continue;
+                    hmem[w] = 0;
+                    const u64 c0 = v & 0xFFFFu, c1 = v >> 16;
+                    if (c0 >= 2) atomicAdd((unsigned long long *)&lsup[2 * w], (unsigned long long)(0ull - c0 * (c0 - 1) / 2));
+                    if (c1 >= 2)
+                        atomicAdd((unsigned long long *)&lsup[2 * w + 1], (unsigned long long)(0ull - c1 * (c1 - 1) / 2));
+                }
+                __syncthreads();
+            }
+            if (nh > 0 && dense) {
+                // back to empty wave hashes
+                for (i32 i = threadIdx.x; i < NW * HCAP; i += BLOCK) hmem[i] = 0xFFFFFFFFu;
+                __syncthreads();
+            }
+            for (i32 b = 0; !dense && b < nh; ++b) {
                 const i32 x = ld_coherent(&lheavy[b]);
                 if (threadIdx.x == 0) s_cnt[1] = 0;
                 __syncthreads();
@@ -1503,17 +1568,23 @@ __global__ __launch_bounds__(FD_BLOCK) void k_tip_fd(FdArgs a) {
                 }
                 __syncthreads();
             }
-            // clamp at the level and retire the batch
+            // clamp at the level, retire the batch and find the next level
+            u64 nmn = ~0ull;
             for (i32 k = threadIdx.x; k < ni; k += BLOCK) {
                 const unsigned char st = ld_coherent(&lst[k]);
                 if (st == 2) {
                     st_coherent(&lst[k], (unsigned char)0);
                 } else if (st == 1) {
-                    const i64 v = ld_coherent(&lsup[k]);
-                    if (v < (i64)kmin) st_coherent(&lsup[k], (i64)kmin);
+                    i64 v = ld_coherent(&lsup[k]);
+                    if (v < (i64)kmin) {
+                        v = (i64)kmin;
+                        st_coherent(&lsup[k], v);
+                    }
+                    nmn = (u64)v < nmn ? (u64)v : nmn;
                 }
             }
             remaining -= nb;
+            kmin = block_min_u64<BLOCK>(nmn, s_red);
             __syncthreads();
         }
     }
