@@ -240,6 +240,10 @@ void mlp_train(Ctx &c, const float *X, const float *Y, const float *Wt, i64 n, i
 void tip_features(Ctx &c, const DevGraph &G, int side, const u64 *sup, float *F);
 void learned_theta_hat(Ctx &c, const DevGraph &G, int side, const u64 *sup, u64 *theta_hat);
 
+// histograms over small key ranges (out += counts / sums of val per key)
+void hist_add_u32(Ctx &c, const i32 *key, i64 n, i32 nb, u32 *out);
+void hist_add_u64(Ctx &c, const i32 *key, const u64 *val, i64 n, i32 nb, u64 *out);
+
 int bits_for(u64 maxval);
 int grid_1d(i64 n, int block = 256, int cap = 16384);
 

@@ -67,6 +67,43 @@ hipEvent_t Ctx::event() {
     return ev_pool[ev_next++];
 }
 
+// Histogram over small key ranges: every block accumulates in LDS and adds
+// its bins to the output once, instead of one device-scope atomic per element
+// on a handful of contended counters.
+constexpr int HIST_LDS = 4096;
+
+template <class T>
+__global__ __launch_bounds__(256) void k_hist_add(const i32 *key, const T *val, i64 n, i32 nb, T *out) {
+    __shared__ T h[HIST_LDS];
+    if (nb <= HIST_LDS) {
+        for (int b = threadIdx.x; b < nb; b += blockDim.x) h[b] = 0;
+        __syncthreads();
+        for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x)
+            atomicAdd(&h[key[i]], val ? val[i] : T(1));
+        __syncthreads();
+        for (int b = threadIdx.x; b < nb; b += blockDim.x)
+            if (h[b]) atomicAdd(&out[b], h[b]);
+    } else {
+        for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x)
+            atomicAdd(&out[key[i]], val ? val[i] : T(1));
+    }
+}
+
+void hist_add_u32(Ctx &c, const i32 *key, i64 n, i32 nb, u32 *out) {
+    if (n <= 0) return;
+    const int g = (int)std::min<i64>((n + 255) / 256, (i64)c.num_cu * 4);
+    hipLaunchKernelGGL(k_hist_add<u32>, dim3(g), dim3(256), 0, c.stream, key, (const u32 *)nullptr, n, nb, out);
+    PBNG_LAUNCH_CHECK();
+}
+
+void hist_add_u64(Ctx &c, const i32 *key, const u64 *val, i64 n, i32 nb, u64 *out) {
+    if (n <= 0) return;
+    const int g = (int)std::min<i64>((n + 255) / 256, (i64)c.num_cu * 4);
+    hipLaunchKernelGGL(k_hist_add<unsigned long long>, dim3(g), dim3(256), 0, c.stream, key,
+                       reinterpret_cast<const unsigned long long *>(val), n, nb, reinterpret_cast<unsigned long long *>(out));
+    PBNG_LAUNCH_CHECK();
+}
+
 hipStream_t Ctx::capture_stream() {
     // non-blocking, default priority
     if (!cap_stream) PBNG_HIP(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));

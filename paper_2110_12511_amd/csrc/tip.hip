@@ -1595,11 +1595,10 @@ __global__ __launch_bounds__(FD_BLOCK) void k_tip_fd(FdArgs a) {
 
 // ---- FD preparation kernels
 
-__global__ void k_part_keys(const i32 *part, i64 nx, u64 *keys, i32 *vals, u32 *pcount) {
+__global__ void k_part_keys(const i32 *part, i64 nx, u64 *keys, i32 *vals) {
     for (i64 x = blockIdx.x * (i64)blockDim.x + threadIdx.x; x < nx; x += (i64)gridDim.x * blockDim.x) {
         keys[x] = (u64)part[x];
         vals[x] = (i32)x;
-        atomicAdd(&pcount[part[x]], 1u);
     }
 }
 
@@ -1634,8 +1633,17 @@ __global__ void k_ypart_keys(const i64 *yrow, const i32 *yadj_orig, const i32 *p
 
 // For X-CSR entry (x, y): the run of N_y (grouped by partition) whose
 // vertices share x's partition; work_p += its length - 1.
-__global__ void k_fd_segments(const i64 *xrow, const i32 *xadj, i64 nx, i64 mx, const i64 *yrow, const i32 *yps,
-                              const i32 *part, i64 *flo, i32 *flen, u64 *work) {
+__global__ __launch_bounds__(256) void k_fd_segments(const i64 *xrow, const i32 *xadj, i64 nx, i64 mx, const i64 *yrow,
+                                                     const i32 *yps, const i32 *part, i64 *flo, i32 *flen, u64 *work,
+                                                     i32 np) {
+    // per-partition work summed in LDS first when the partitions fit
+    constexpr int HB = 2048;
+    __shared__ unsigned long long h[HB];
+    const bool priv = np <= HB;
+    if (priv) {
+        for (int b = threadIdx.x; b < np; b += blockDim.x) h[b] = 0;
+        __syncthreads();
+    }
     for (i64 j = blockIdx.x * (i64)blockDim.x + threadIdx.x; j < mx; j += (i64)gridDim.x * blockDim.x) {
         i64 x = row_of_t(xrow, nx, j);
         i32 p = part[x];
@@ -1654,7 +1662,13 @@ __global__ void k_fd_segments(const i64 *xrow, const i32 *xadj, i64 nx, i64 mx, 
         }
         flo[j] = s;
         flen[j] = (i32)(lo - s);
-        atomicAdd((unsigned long long *)&work[p], (unsigned long long)(lo - s - 1));
+        if (priv) atomicAdd(&h[p], (unsigned long long)(lo - s - 1));
+        else atomicAdd((unsigned long long *)&work[p], (unsigned long long)(lo - s - 1));
+    }
+    if (priv) {
+        __syncthreads();
+        for (int b = threadIdx.x; b < np; b += blockDim.x)
+            if (h[b]) atomicAdd((unsigned long long *)&work[b], h[b]);
     }
 }
 
@@ -2067,7 +2081,8 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
     i32 *pv = c.alloc<i32>(std::max<i64>(nx, m));
     u32 *pcount = c.alloc<u32>(np);
     PBNG_HIP(hipMemsetAsync(pcount, 0, sizeof(u32) * np, s));
-    hipLaunchKernelGGL(k_part_keys, dim3(gx), dim3(256), 0, s, (const i32 *)part, nx, pk, pv, pcount);
+    hipLaunchKernelGGL(k_part_keys, dim3(gx), dim3(256), 0, s, (const i32 *)part, nx, pk, pv);
+    hist_add_u32(c, part, nx, np, pcount);
     PBNG_LAUNCH_CHECK();
     u64 *sk;
     i32 *xs;
@@ -2091,8 +2106,8 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
         PBNG_LAUNCH_CHECK();
         u64 *ysk;
         radix_sort_u64(c, yk, yv, m, bits_for((u64)ny * (u64)np), &ysk, &yps);
-        hipLaunchKernelGGL(k_fd_segments, dim3(grid_1d(m)), dim3(256), 0, s, xrow, xadj, nx, m, yrow, (const i32 *)yps,
-                           (const i32 *)part, flo, flen, work);
+        hipLaunchKernelGGL(k_fd_segments, dim3(std::min<i64>(grid_1d(m), (i64)c.num_cu * 8)), dim3(256), 0, s, xrow, xadj,
+                           nx, m, yrow, (const i32 *)yps, (const i32 *)part, flo, flen, work, np);
         PBNG_LAUNCH_CHECK();
     }
     // LPT order

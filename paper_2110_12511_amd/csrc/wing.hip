@@ -280,11 +280,10 @@ __global__ void w_random_pick(WingCtl *ctl, const u64 *mn, const u64 *mx, u64 se
 
 // ------------------------------------------------------------------ FD preparation
 
-__global__ void w_part_keys(const i32 *part, i64 m, u64 *keys, i32 *vals, u32 *pcount) {
+__global__ void w_part_keys(const i32 *part, i64 m, u64 *keys, i32 *vals) {
     for (i64 e = blockIdx.x * (i64)blockDim.x + threadIdx.x; e < m; e += (i64)gridDim.x * blockDim.x) {
         keys[e] = (u64)part[e];
         vals[e] = (i32)e;
-        atomicAdd(&pcount[part[e]], 1u);
     }
 }
 
@@ -399,15 +398,7 @@ __global__ void w_part_first_inst(const i32 *ipart, i64 ninst, i64 *pfirst) {
         if (t == 0 || ipart[t] != ipart[t - 1]) pfirst[ipart[t]] = t;
 }
 
-__global__ void w_inst_count(const i32 *ipart, i64 ninst, u32 *cnt) {
-    for (i64 t = blockIdx.x * (i64)blockDim.x + threadIdx.x; t < ninst; t += (i64)gridDim.x * blockDim.x)
-        atomicAdd(&cnt[ipart[t]], 1u);
-}
 
-__global__ void w_fd_work(const i32 *part, const u64 *init, i64 m, u64 *work) {
-    for (i64 e = blockIdx.x * (i64)blockDim.x + threadIdx.x; e < m; e += (i64)gridDim.x * blockDim.x)
-        atomicAdd((unsigned long long *)&work[part[e]], (unsigned long long)init[e]);
-}
 
 __global__ void w_lpt_keys(const u64 *work, i32 np, u64 maxw, u64 *keys, i32 *vals) {
     for (i64 p = blockIdx.x * (i64)blockDim.x + threadIdx.x; p < np; p += (i64)gridDim.x * blockDim.x) {
@@ -1054,7 +1045,8 @@ void wing_decompose(Ctx &c, const DevGraph &G, const pbng_opts &o, u64 *theta) {
     i32 *ev = c.alloc<i32>(m);
     u32 *pcount = c.alloc<u32>(np);
     PBNG_HIP(hipMemsetAsync(pcount, 0, sizeof(u32) * np, s));
-    hipLaunchKernelGGL(w_part_keys, dim3(gm), dim3(256), 0, s, (const i32 *)part, m, ek, ev, pcount);
+    hipLaunchKernelGGL(w_part_keys, dim3(gm), dim3(256), 0, s, (const i32 *)part, m, ek, ev);
+    hist_add_u32(c, part, m, np, pcount);
     PBNG_LAUNCH_CHECK();
     u64 *eks;
     i32 *es;
@@ -1141,7 +1133,7 @@ void wing_decompose(Ctx &c, const DevGraph &G, const pbng_opts &o, u64 *theta) {
     u64 *wm = c.alloc<u64>(4);
     PBNG_HIP(hipMemsetAsync(work, 0, sizeof(u64) * np, s));
     PBNG_HIP(hipMemsetAsync(wm, 0, 4 * sizeof(u64), s));
-    hipLaunchKernelGGL(w_fd_work, dim3(gm), dim3(256), 0, s, (const i32 *)part, (const u64 *)init, m, work);
+    hist_add_u64(c, part, init, m, np, work);
     hipLaunchKernelGGL(w_max_u64, dim3(grid_1d(np)), dim3(256), 0, s, (const u64 *)work, (i64)np, wm, wm + 1);
     hipLaunchKernelGGL(w_max_u64, dim3(grid_1d(np)), dim3(256), 0, s, (const u64 *)pc64, (i64)np, wm + 2, (u64 *)nullptr);
     PBNG_LAUNCH_CHECK();
@@ -1154,7 +1146,7 @@ void wing_decompose(Ctx &c, const DevGraph &G, const pbng_opts &o, u64 *theta) {
         u32 *icnt = c.alloc<u32>(np);
         i64 *icnt64 = c.alloc<i64>(np);
         PBNG_HIP(hipMemsetAsync(icnt, 0, sizeof(u32) * np, s));
-        hipLaunchKernelGGL(w_inst_count, dim3(grid_1d(ninst)), dim3(256), 0, s, (const i32 *)ipart, ninst, icnt);
+        hist_add_u32(c, ipart, ninst, np, icnt);
         hipLaunchKernelGGL(w_u32_to_i64, dim3(grid_1d(np)), dim3(256), 0, s, (const u32 *)icnt, (i64)np, icnt64);
         PBNG_HIP(hipMemsetAsync(wm + 3, 0, sizeof(u64), s));
         hipLaunchKernelGGL(w_max_u64, dim3(grid_1d(np)), dim3(256), 0, s, (const u64 *)icnt64, (i64)np, wm + 3, (u64 *)nullptr);
