@@ -64,7 +64,7 @@ constexpr u32 PULL_MIN_F = 0xFFFFFFFFu;
 // 2^TILE_LOG consecutive X ids, two 16-bit counters per 32-bit word.
 constexpr int TILE_LOG = 16;
 // active vertices with more wedges than this take the key-tile path
-constexpr i64 HUGE_W = i64(1) << 18;
+constexpr i64 HUGE_W = i64(1) << 16;
 // LDS hash slots of the (vertex, key range) path
 constexpr int H_LOGCAP = 14;
 // active vertices with 2..PAIR_DMAX neighbours whose pairwise list
