@@ -31,7 +31,8 @@ sys.path.insert(0, ROOT)
 METRIC = "wedges/s + tip/wing decomposition time, learned vs plain CD bounds, 1 GPU"
 HBM_PEAK_GBS = 8000.0
 # kernel behind each timed class that holds a single kernel
-CLASS_KERNEL = {"tip_hrange": "k_tip_peel_hrange<14>", "fd": "k_tip_fd / k_wing_fd", "dense": "m_gram"}
+CLASS_KERNEL = {"tip_hrange": "k_tip_peel_hrange<14>", "tip_tiled": "k_tip_peel_tiled<16>", "fd": "k_tip_fd / k_wing_fd",
+                "dense": "m_gram"}
 
 WORKLOADS = {
     # name: (graph config, kind, P); kinds: tip (both sides), tip_u (side U),
@@ -110,7 +111,7 @@ def profile_traffic(kernel_class, workload):
     None when there is none or the kernel's sources changed since."""
     import re
 
-    names = {"tip_hrange": "k_tip_peel_hrange"}
+    names = {"tip_hrange": "k_tip_peel_hrange", "tip_tiled": "k_tip_peel_tiled"}
     if kernel_class not in names:
         return None
     path = os.path.join(ROOT, "profiles", f"{names[kernel_class]}__{workload}.md")

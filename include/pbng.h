@@ -102,7 +102,9 @@ enum {
     PBNG_K_DENSE = 4,   /* int8 matrix-core hub tiles                       */
     PBNG_K_TIP_HRANGE = 5, /* coarse-grained tip peel: the (vertex, key
                               range) LDS hash kernel alone                  */
-    PBNG_K_NCLASS = 6
+    PBNG_K_TIP_TILED = 6,  /* coarse-grained tip peel: the (vertex, key
+                              tile) LDS counter kernel alone                */
+    PBNG_K_NCLASS = 7
 };
 
 typedef struct {

@@ -60,8 +60,8 @@ class Opts(ctypes.Structure):
     ]
 
 
-K_COUNT, K_TIP_PEEL, K_FD, K_WING_CD, K_DENSE, K_TIP_HRANGE, K_NCLASS = 0, 1, 2, 3, 4, 5, 6
-K_NAMES = ["count", "tip_peel", "fd", "wing_cd", "dense", "tip_hrange"]
+K_COUNT, K_TIP_PEEL, K_FD, K_WING_CD, K_DENSE, K_TIP_HRANGE, K_TIP_TILED, K_NCLASS = 0, 1, 2, 3, 4, 5, 6, 7
+K_NAMES = ["count", "tip_peel", "fd", "wing_cd", "dense", "tip_hrange", "tip_tiled"]
 F_KERNEL_TIMING = 0x8
 F_HOST_ROUNDS = 0x10
 

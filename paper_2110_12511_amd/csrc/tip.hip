@@ -1998,10 +1998,16 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
                 PeelArgs pm = pa;
                 pm.items = bins + nx;
                 c.kbegin(PBNG_K_TIP_PEEL);
-                if (huge_tiled)
+                if (huge_tiled) {
+                    c.kend(PBNG_K_TIP_PEEL);
+                    PeelArgs pk = pd;
+                    pk.kc = c.kctr + PBNG_K_TIP_TILED;
+                    c.kbegin(PBNG_K_TIP_TILED);
                     hipLaunchKernelGGL(k_tip_peel_tiled<TILE_LOG>, dim3(std::min<i64>(tslots, (i64)nF * ntiles)), dim3(512), 0, s,
-                                       pd, 3);
-                else if (huge_bits)
+                                       pk, 3);
+                    c.kend(PBNG_K_TIP_TILED);
+                    c.kbegin(PBNG_K_TIP_PEEL);
+                } else if (huge_bits)
                     hipLaunchKernelGGL(k_tip_peel_bits<BITS_NBW>, dim3(std::min<i64>(slots, nF)), dim3(512), 0, s, pd, 3);
                 else
                     hipLaunchKernelGGL(k_tip_peel_dense, dim3(std::min<i64>(slots, nF)), dim3(256), 0, s, pd, 3);
