@@ -127,7 +127,8 @@ typedef struct {
     int32_t tile_w;     /* coarse-grained tip rounds: active vertices with
                            more live wedges than this count in LDS key tiles,
                            others in LDS hash ranges; 0 = library default
-                           (2^16), negative = never (schedule only)          */
+                           (the larger of 2^16 and 4096 per 2^16-vertex tile
+                           of the side), negative = never (schedule only)    */
     int32_t batch_edges;/* batch calls: most edges packed into one union
                            graph; 0 = library default (2^28)                 */
     int32_t wide_work;  /* wing: fine-grained work above which a partition

@@ -595,9 +595,14 @@ __global__ __launch_bounds__(512) void k_count_tiled(CountArgs a, const u32 *off
 
 constexpr i64 SMALL_W = 512, MEDIUM_W = 4096;
 
+// Large starts go to the key-tile kernel (bin 2) when the vertex-count modes
+// run and they have at least TILE_MIN_W wedges per tile of their keys on
+// average, else to the HBM-counter kernel (bin 3).
+constexpr i64 TILE_MIN_W = 2048;
+
 __global__ void k_bin_starts(const i64 *wsum, const unsigned char *lclass, const unsigned char *alive, i64 n, i32 *lists,
-                             u32 *counts) {
-    // lists: [3][n]; counts: [3]; one atomic per wave and bin
+                             u32 *counts, int tiles_ok) {
+    // lists: [4][n]; counts: [4]; one atomic per wave and bin
     const i64 stride = (i64)gridDim.x * blockDim.x;
     const i64 nn = (n + WAVE - 1) / WAVE * WAVE;
     for (i64 s = blockIdx.x * (i64)blockDim.x + threadIdx.x; s < nn; s += stride) {
@@ -605,9 +610,16 @@ __global__ void k_bin_starts(const i64 *wsum, const unsigned char *lclass, const
         if (s < n) {
             const i64 w = wsum[s];
             const bool skip = w == 0 || (alive && !alive[s]) || (lclass && lclass[s] == LC_XHUB);
-            if (!skip) b = w <= SMALL_W ? 0 : (w <= MEDIUM_W ? 1 : 2);
+            if (!skip) {
+                if (w <= SMALL_W) b = 0;
+                else if (w <= MEDIUM_W) b = 1;
+                else {
+                    const i64 tiles = (s + (i64(1) << CT_LOG) - 1) >> CT_LOG;
+                    b = tiles_ok && w >= tiles * TILE_MIN_W ? 2 : 3;
+                }
+            }
         }
-        for (int k = 0; k < 3; ++k) {
+        for (int k = 0; k < 4; ++k) {
             const u32 p = wave_append(&counts[k], b == k);
             if (b == k) lists[(i64)k * n + p] = (i32)s;
         }
@@ -621,32 +633,31 @@ static int gridN(i64 n) {
 
 struct Bins {
     i32 *lists;
-    u32 cnt[3];
+    u32 cnt[4];
 };
 
-static Bins bin_starts(Ctx &c, const DevGraph &G, const unsigned char *alive, const unsigned char *lclass = nullptr) {
+static Bins bin_starts(Ctx &c, const DevGraph &G, const unsigned char *alive, const unsigned char *lclass, bool tiles_ok) {
     Bins b;
-    b.lists = c.alloc<i32>(3 * G.n);
+    b.lists = c.alloc<i32>(4 * G.n);
     u32 *counts = c.alloc<u32>(4);
     PBNG_HIP(hipMemsetAsync(counts, 0, 4 * sizeof(u32), c.stream));
     if (G.n) {
         hipLaunchKernelGGL(k_bin_starts, dim3(gridN(G.n)), dim3(256), 0, c.stream, (const i64 *)G.wsum, lclass, alive, G.n,
-                           b.lists, counts);
+                           b.lists, counts, tiles_ok ? 1 : 0);
         PBNG_LAUNCH_CHECK();
     }
-    PBNG_HIP(hipMemcpyAsync(b.cnt, counts, 3 * sizeof(u32), hipMemcpyDeviceToHost, c.stream));
+    PBNG_HIP(hipMemcpyAsync(b.cnt, counts, 4 * sizeof(u32), hipMemcpyDeviceToHost, c.stream));
     PBNG_HIP(hipStreamSynchronize(c.stream));
     return b;
 }
 
 template <int MODE>
 static void launch_all(Ctx &c, const DevGraph &G, CountArgs a, const Bins &b) {
-    u32 *next = c.alloc<u32>(3);
-    PBNG_HIP(hipMemsetAsync(next, 0, 3 * sizeof(u32), c.stream));
+    u32 *next = c.alloc<u32>(4);
+    PBNG_HIP(hipMemsetAsync(next, 0, 4 * sizeof(u32), c.stream));
     a.kc = c.kctr + PBNG_K_COUNT;
-    const int slots = (int)std::min<i64>(b.cnt[2], (i64)c.num_cu);
-    constexpr bool tiled = MODE == M_XSIDE || MODE == M_VERTEX;
-    if (b.cnt[2] && !tiled) {
+    const int slots = (int)std::min<i64>(b.cnt[3], (i64)c.num_cu);
+    if (b.cnt[3]) {
         a.dcnt = c.alloc<u32>((i64)slots * G.n);
         a.dtouch = c.alloc<i32>((i64)slots * G.n);
         a.dbid = (MODE & M_BE_FILL) ? c.alloc<i32>((i64)slots * G.n) : nullptr;
@@ -656,21 +667,26 @@ static void launch_all(Ctx &c, const DevGraph &G, CountArgs a, const Bins &b) {
     }
     c.kbegin(PBNG_K_COUNT);
     // large starts first: they are the long tail
-    if (b.cnt[2]) {
-        a.starts = b.lists + 2 * G.n;
-        a.nstarts = b.cnt[2];
-        a.next = next + 2;
-        if constexpr (MODE == M_XSIDE || MODE == M_VERTEX) {
+    if (b.cnt[3]) {
+        a.starts = b.lists + 3 * G.n;
+        a.nstarts = b.cnt[3];
+        a.next = next + 3;
+        hipLaunchKernelGGL(k_count_dense<MODE>, dim3(slots), dim3(256), 0, c.stream, a);
+        PBNG_LAUNCH_CHECK();
+    }
+    if constexpr (MODE == M_XSIDE || MODE == M_VERTEX) {
+        if (b.cnt[2]) {
+            a.starts = b.lists + 2 * G.n;
+            a.nstarts = b.cnt[2];
+            a.next = next + 2;
             u32 *toff = c.alloc<u32>((i64)b.cnt[2] + 1);
             u32 *ttot = c.alloc<u32>(1);
             hipLaunchKernelGGL(k_count_tiles, dim3(1), dim3(1024), 0, c.stream, (const i32 *)a.starts, (u32)b.cnt[2], toff,
                                ttot);
             hipLaunchKernelGGL(k_count_tiled<MODE>, dim3(c.num_cu), dim3(512), 0, c.stream, a, (const u32 *)toff,
                                (const u32 *)ttot);
-        } else {
-            hipLaunchKernelGGL(k_count_dense<MODE>, dim3(slots), dim3(256), 0, c.stream, a);
+            PBNG_LAUNCH_CHECK();
         }
-        PBNG_LAUNCH_CHECK();
     }
     if (b.cnt[1]) {
         a.starts = b.lists + G.n;
@@ -711,7 +727,7 @@ u64 count_pass(Ctx &c, const DevGraph &G, u64 *sup_label, u64 *sup_edge, const u
     PBNG_HIP(hipMemsetAsync(a.wedges, 0, sizeof(u64), c.stream));
     if (sup_label) PBNG_HIP(hipMemsetAsync(sup_label, 0, sizeof(u64) * (G.n ? G.n : 1), c.stream));
     if (sup_edge) PBNG_HIP(hipMemsetAsync(sup_edge, 0, sizeof(u64) * (G.m ? G.m : 1), c.stream));
-    Bins b = bin_starts(c, G, alive);
+    Bins b = bin_starts(c, G, alive, nullptr, sup_label && !sup_edge);
     if (sup_label && sup_edge) launch_all<M_VERTEX | M_EDGE>(c, G, a, b);
     else if (sup_label) launch_all<M_VERTEX>(c, G, a, b);
     else if (sup_edge) launch_all<M_EDGE>(c, G, a, b);
@@ -725,7 +741,7 @@ u64 count_pass_xside(Ctx &c, const DevGraph &G, u64 *sup_label, const unsigned c
     a.wedges = c.alloc<u64>(1);
     PBNG_HIP(hipMemsetAsync(a.wedges, 0, sizeof(u64), c.stream));
     PBNG_HIP(hipMemsetAsync(sup_label, 0, sizeof(u64) * (G.n ? G.n : 1), c.stream));
-    Bins b = bin_starts(c, G, nullptr, lclass);
+    Bins b = bin_starts(c, G, nullptr, lclass, true);
     launch_all<M_XSIDE>(c, G, a, b);
     return read_scalar<u64>(c, a.wedges);
 }
@@ -781,7 +797,7 @@ void build_be_index(Ctx &c, const DevGraph &G, BEIndex &I, u64 *sup_edge) {
     CountArgs a = base_args(G);
     a.wedges = c.alloc<u64>(1);
     PBNG_HIP(hipMemsetAsync(a.wedges, 0, sizeof(u64), c.stream));
-    Bins b = bin_starts(c, G, nullptr);
+    Bins b = bin_starts(c, G, nullptr, nullptr, false);
     // sizes
     a.bcnt = c.alloc<i64>(n);
     a.pcnt = c.alloc<i64>(n);

@@ -1800,7 +1800,9 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
     const char *heavy_env = getenv("PBNG_HEAVY");
     const bool huge_bits = heavy_env && heavy_env[0] == 'b' && nx <= (i64)BITS_NBW * 32;
     const bool huge_tiled = !huge_bits && (u64)nx * (u64)ntiles < (u64(1) << 32);
-    const u64 huge_w = o.tile_w == 0 ? (u64)HUGE_W : (o.tile_w < 0 ? ~0ull : (u64)o.tile_w);
+    // default threshold: at least 4096 wedges per key tile on average
+    const u64 huge_w = o.tile_w == 0 ? std::max<u64>((u64)HUGE_W, (u64)ntiles * 4096u)
+                                     : (o.tile_w < 0 ? ~0ull : (u64)o.tile_w);
     u32 *hoff = c.alloc<u32>(nx + 1);
     u32 *htotal = c.alloc<u32>(1);
     const char *pull_env = getenv("PBNG_PULL_MIN_F");
