@@ -22,6 +22,30 @@ struct SelState {
     u64 done;      // 1 when the total was below target (result = maxkey)
 };
 
+// Per-block sum and maximum, then one pair of device atomics per block (a
+// per-wave pair would queue thousands of same-address atomics).
+__device__ __forceinline__ void block_sum_max(u64 t, u64 mx, u64 *sum_out, u64 *max_out) {
+    __shared__ u64 s_t[256 / WAVE], s_m[256 / WAVE];
+    for (int d = WAVE / 2; d > 0; d >>= 1) {
+        t += __shfl_down(t, d, WAVE);
+        const u64 o = __shfl_down(mx, d, WAVE);
+        mx = o > mx ? o : mx;
+    }
+    if ((threadIdx.x & (WAVE - 1)) == 0) {
+        s_t[threadIdx.x / WAVE] = t;
+        s_m[threadIdx.x / WAVE] = mx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < 256 / WAVE; ++i) {
+            t += s_t[i];
+            mx = s_m[i] > mx ? s_m[i] : mx;
+        }
+        if (t) atomicAdd((unsigned long long *)sum_out, (unsigned long long)t);
+        if (max_out && mx) atomicMax((unsigned long long *)max_out, (unsigned long long)mx);
+    }
+}
+
 __global__ __launch_bounds__(256) void k_sel_total(const u64 *key, const u64 *w, const unsigned char *state,
                                                   unsigned char alive, i64 n, SelState *st) {
     u64 t = 0, mx = 0;
@@ -31,15 +55,7 @@ __global__ __launch_bounds__(256) void k_sel_total(const u64 *key, const u64 *w,
         u64 k = key[i];
         mx = k > mx ? k : mx;
     }
-    for (int d = WAVE / 2; d > 0; d >>= 1) {
-        t += __shfl_down(t, d, WAVE);
-        u64 o = __shfl_down(mx, d, WAVE);
-        mx = o > mx ? o : mx;
-    }
-    if ((threadIdx.x & 63) == 0) {
-        atomicAdd((unsigned long long *)&st->total, (unsigned long long)t);
-        atomicMax((unsigned long long *)&st->maxkey, (unsigned long long)mx);
-    }
+    block_sum_max(t, mx, &st->total, &st->maxkey);
 }
 
 // Target of the plain rule (Section 3.1.3): the alive work spread over the
@@ -71,7 +87,9 @@ __global__ __launch_bounds__(256) void k_sel_hist(const u64 *key, const u64 *w, 
     __shared__ u64 h[256];
     h[threadIdx.x] = 0;
     __syncthreads();
-    if (!st->done) {
+    // a level above the largest key's top bit has digit 0 for every key:
+    // nothing to count (the pick keeps digit 0)
+    if (!st->done && (st->maxkey >> shift) != 0) {
         const u64 pre = st->prefix;
         const int hs = shift + 8;
         for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) {
@@ -85,25 +103,30 @@ __global__ __launch_bounds__(256) void k_sel_hist(const u64 *key, const u64 *w, 
     if (h[threadIdx.x]) atomicAdd((unsigned long long *)&hist[threadIdx.x], (unsigned long long)h[threadIdx.x]);
 }
 
-__global__ void k_sel_pick(SelState *st, int shift, u64 *hist) {
-    // one thread: the smallest digit whose cumulative weight covers the
-    // remaining target; clears the histogram for the next level
-    const bool active = !st->done;
-    u64 rem = st->rem, cum = 0;
-    int pick = -1;
-    for (int d = 0; d < 256; ++d) {
-        u64 h = hist[d];
-        if (active && pick < 0) {
-            if (h > 0 && cum + h >= rem) {
-                pick = d;
-                st->rem = rem - cum;
-            } else {
-                cum += h;
-            }
-        }
-        hist[d] = 0;
+// The smallest digit whose cumulative weight covers the remaining target
+// (256 threads, one digit each: inclusive prefix in LDS, then the count of
+// digits still below the target is the pick); clears the histogram for the
+// next level.
+__global__ __launch_bounds__(256) void k_sel_pick(SelState *st, int shift, u64 *hist) {
+    __shared__ u64 sh[256];
+    const int d = threadIdx.x;
+    const u64 h = hist[d];
+    hist[d] = 0;
+    if (st->done || (st->maxkey >> shift) == 0) return;  // block-uniform
+    sh[d] = h;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const u64 v = d >= off ? sh[d - off] : 0;
+        __syncthreads();
+        sh[d] += v;
+        __syncthreads();
     }
-    if (active) st->prefix |= (u64)(pick < 0 ? 255 : pick) << shift;
+    const u64 rem = st->rem;
+    const int below = __syncthreads_count(sh[d] < rem ? 1 : 0);
+    if (d == 0) {
+        if (below < 256) st->rem = rem - (below ? sh[below - 1] : 0);
+        st->prefix |= (u64)(below < 256 ? below : 255) << shift;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_sel_work(const u64 *key, const u64 *w, const unsigned char *state,
@@ -113,8 +136,7 @@ __global__ __launch_bounds__(256) void k_sel_work(const u64 *key, const u64 *w, 
     u64 t = 0;
     for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x)
         if (state[i] == alive && key[i] <= s) t += w[i];
-    for (int d = WAVE / 2; d > 0; d >>= 1) t += __shfl_down(t, d, WAVE);
-    if ((threadIdx.x & 63) == 0) atomicAdd((unsigned long long *)&st->work, (unsigned long long)t);
+    block_sum_max(t, 0, &st->work, nullptr);
 }
 
 __global__ void k_sel_finish(SelState *st, u64 *s_out, u64 *work_out) {
@@ -125,7 +147,7 @@ __global__ void k_sel_finish(SelState *st, u64 *s_out, u64 *work_out) {
 
 static int grid_sel(i64 n) {
     i64 g = (n + 255) / 256;
-    return (int)(g < 1 ? 1 : (g > 2048 ? 2048 : g));
+    return (int)(g < 1 ? 1 : (g > 512 ? 512 : g));
 }
 
 // All launches are asynchronous on the context stream; results stay on the
@@ -147,7 +169,7 @@ void weighted_select(Ctx &c, const u64 *key, const u64 *w, const unsigned char *
         hipLaunchKernelGGL(k_sel_hist, dim3(grid_sel(n)), dim3(256), 0, c.stream, key, w, state, alive, n, shift,
                            (const SelState *)st, hist);
         PBNG_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_sel_pick, dim3(1), dim3(1), 0, c.stream, st, shift, hist);
+        hipLaunchKernelGGL(k_sel_pick, dim3(1), dim3(256), 0, c.stream, st, shift, hist);
         PBNG_LAUNCH_CHECK();
     }
     hipLaunchKernelGGL(k_sel_work, dim3(grid_sel(n)), dim3(256), 0, c.stream, key, w, state, alive, n, st);

@@ -107,16 +107,19 @@ struct ItemSmem {
 };
 
 // Every wedge x -> y -> x' of an active x over the live Y lists is counted
-// per x'; then every alive x' with c >= 2 loses C(c, 2) of its support; after
-// the round the alive vertices whose support fell below the bound form the
-// next active set.  Keys that are not alive (other active vertices) are
-// dropped in that epilogue, once per key.
+// per x'; then every x' with c >= 2 loses C(c, 2) of its support; after the
+// round the alive vertices whose support fell below the bound form the next
+// active set.
 // Support updates of a batch of NB (key, count) pairs.  Keys < 0 or counts
-// < 2 are skipped; so are vertices that are not alive (peeled earlier or
-// active this round).  The subtractions are fire-and-forget atomics (no
-// returned value to wait for): the next active set is found after the round
-// by k_sweep_frontier, as every alive vertex whose support fell below the
-// bound, the same set the crossings would give.
+// < 2 are skipped.  Keys that are not alive (other vertices active this
+// round, and peeled ones when list compaction is off) are updated too: the
+// support of a vertex is never read after it leaves the alive set (every
+// reader filters on ST_ALIVE, and the fine-grained phase starts from the
+// snapshot taken when its partition began), so the update is harmless and
+// saves a dependent state load per key.  The subtractions are
+// fire-and-forget atomics (no returned value to wait for): the next active
+// set is found after the round by k_sweep_frontier, as every alive vertex
+// whose support fell below the bound, the same set the crossings would give.
 template <int NB>
 __device__ __forceinline__ void apply_updates(const PeelArgs &a, u64 B, const i32 (&key)[NB], const u32 (&cnt)[NB],
                                               Tally &t) {
@@ -125,15 +128,54 @@ __device__ __forceinline__ void apply_updates(const PeelArgs &a, u64 B, const i3
 #pragma unroll
     for (int q = 0; q < NB; ++q) ok[q] = key[q] >= 0 && cnt[q] >= 2;
 #pragma unroll
-    for (int q = 0; q < NB; ++q)
-        if (ok[q]) ok[q] = a.st[key[q]] == ST_ALIVE;
-#pragma unroll
     for (int q = 0; q < NB; ++q) {
         if (!ok[q]) continue;
         const u64 dd = (u64)cnt[q] * (u64)(cnt[q] - 1) / 2;
         atomicAdd((unsigned long long *)&a.sup[key[q]], (unsigned long long)(0ull - dd));
         ++t.atomics;
     }
+}
+
+// Far ends of the wedges k0 .. k0 + UNR - 1 of a chunk of neighbour lists
+// whose wedge counts have inclusive prefix pre[0..last] and whose runs start
+// at yadj[moff[l]]; wedges at or past tot give x (skipped by the caller).
+// One binary search finds the list of k0; the rest of the run walks forward,
+// reading the next prefix only where a list ends.  All UNR addresses are
+// formed first and every load is issued unconditionally (a wedge past tot
+// reads yadj[0], which exists whenever tot > 0), so the loads are in flight
+// together and the thread waits once.
+template <int UNR>
+__device__ __forceinline__ void run_ends(const i32 *yadj, const i32 *pre, const i64 *moff, int last, i32 k0, i32 tot,
+                                         i32 x, i32 (&xq)[UNR]) {
+    i64 idx[UNR];
+#pragma unroll
+    for (int q = 0; q < UNR; ++q) idx[q] = 0;
+    if (k0 < tot) {
+        int l = 0, h = last;
+        while (l < h) {
+            const int md = (l + h) >> 1;
+            if (pre[md] > k0) h = md; else l = md + 1;
+        }
+        i32 end = pre[l];
+        i64 base = moff[l] - (l ? pre[l - 1] : 0);
+#pragma unroll
+        for (int q = 0; q < UNR; ++q) {
+            const i32 k = k0 + q;
+            if (k < tot) {
+                while (k >= end) {
+                    ++l;
+                    base = moff[l] - end;
+                    end = pre[l];
+                }
+                idx[q] = base + k;
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < UNR; ++q) xq[q] = yadj[idx[q]];
+#pragma unroll
+    for (int q = 0; q < UNR; ++q)
+        if (k0 + q >= tot) xq[q] = x;
 }
 
 // next active set of a push round: alive vertices below the bound
@@ -347,25 +389,12 @@ __global__ __launch_bounds__(512) void k_tip_peel_tiled(PeelArgs a, int bin) {
             s_moff[threadIdx.x] = moff;
             __syncthreads();
             const int last = (d - cb < BLOCK ? d - cb : BLOCK) - 1;
-            constexpr int UN = 4;
-            for (i32 k0 = threadIdx.x; k0 < tot; k0 += UN * BLOCK) {
-                i32 xq[UN];
+            constexpr int UNR = 8;
+            for (i32 kb = 0; kb < tot; kb += UNR * BLOCK) {
+                i32 xq[UNR];
+                run_ends<UNR>(a.yadj, s_pre, s_moff, last, kb + (i32)threadIdx.x * UNR, tot, x, xq);
 #pragma unroll
-                for (int q = 0; q < UN; ++q) {
-                    const i32 k = k0 + q * BLOCK;
-                    xq[q] = x;
-                    if (k < tot) {
-                        int lo = 0, hi = last;
-                        while (lo < hi) {
-                            int md = (lo + hi) >> 1;
-                            if (s_pre[md] > k) hi = md; else lo = md + 1;
-                        }
-                        const i32 before = lo ? s_pre[lo - 1] : 0;
-                        xq[q] = a.yadj[s_moff[lo] + (k - before)];
-                    }
-                }
-#pragma unroll
-                for (int q = 0; q < UN; ++q) {
+                for (int q = 0; q < UNR; ++q) {
                     const i32 xp = xq[q];
                     if (xp == x) continue;
                     ++tl.wedges;
@@ -524,55 +553,52 @@ __global__ __launch_bounds__(512) void k_tip_peel_hrange(PeelArgs a, int bin, co
             s_moff[threadIdx.x] = moff;
             __syncthreads();
             const int last = (d - cb < BLOCK ? d - cb : BLOCK) - 1;
-            constexpr int UN = 4;
-            for (i32 k0 = threadIdx.x; k0 < tot; k0 += UN * BLOCK) {
-                // the far ends of UN wedges are loaded together
-                i32 xq[UN];
+            constexpr int UNR = 8;
+            for (i32 kb = 0; kb < tot; kb += UNR * BLOCK) {
+                i32 xq[UNR];
+                run_ends<UNR>(a.yadj, s_pre, s_moff, last, kb + (i32)threadIdx.x * UNR, tot, x, xq);
+                // Linear probing over H_PROBE slots.  The first probe of all
+                // UNR keys is one batch of compare-and-swaps issued together
+                // (claim the home slot if empty; a skipped wedge compares
+                // against -2, which no slot holds, so it writes nothing), so
+                // most keys settle after one LDS round trip shared by the
+                // batch; the rest continue one by one from the next slot.
+                u32 hs[UNR];
+                i32 kk[UNR];
 #pragma unroll
-                for (int q = 0; q < UN; ++q) {
-                    const i32 k = k0 + q * BLOCK;
-                    xq[q] = x;
-                    if (k < tot) {
-                        int l = 0, h = last;
-                        while (l < h) {
-                            const int md = (l + h) >> 1;
-                            if (s_pre[md] > k) h = md; else l = md + 1;
-                        }
-                        const i32 before = l ? s_pre[l - 1] : 0;
-                        xq[q] = a.yadj[s_moff[l] + (k - before)];
-                    }
+                for (int q = 0; q < UNR; ++q) {
+                    hs[q] = hash32((u32)xq[q]) >> (32 - LOGCAP);
+                    kk[q] = atomicCAS(&keys[hs[q]], xq[q] != x ? -1 : -2, xq[q]);
                 }
 #pragma unroll
-                for (int q = 0; q < UN; ++q) {
-                const i32 xp = xq[q];
-                if (xp == x) continue;
-                ++tl.wedges;
-                u32 hs = hash32((u32)xp) >> (32 - LOGCAP);
-                bool done = false;
-                for (int p = 0; p < H_PROBE; ++p) {
-                    const i32 kk = keys[hs];
-                    if (kk == xp) {
-                        done = true;
-                        break;
-                    }
-                    if (kk == -1) {
-                        const i32 prev = atomicCAS(&keys[hs], -1, xp);
-                        if (prev == -1 || prev == xp) {
+                for (int q = 0; q < UNR; ++q)
+                    if (kk[q] == -1) kk[q] = xq[q];
+#pragma unroll
+                for (int q = 0; q < UNR; ++q) {
+                    const i32 xp = xq[q];
+                    if (xp == x) continue;
+                    ++tl.wedges;
+                    u32 h = hs[q];
+                    bool done = kk[q] == xp;
+                    for (int p = 1; p < H_PROBE && !done; ++p) {
+                        h = (h + 1) & (CAP - 1);
+                        const i32 k2 = keys[h];
+                        if (k2 == xp) {
                             done = true;
-                            break;
+                        } else if (k2 == -1) {
+                            const i32 prev = atomicCAS(&keys[h], -1, xp);
+                            done = prev == -1 || prev == xp;
                         }
                     }
-                    hs = (hs + 1) & (CAP - 1);
-                }
-                if (done) {
-                    atomicAdd(&vals[hs], 1u);
-                } else {
-                    const u32 old = __hip_atomic_fetch_add(&gc[xp], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    if (old == 0) {
-                        const u32 t = atomicAdd(&s_ntouch, 1u);
-                        __hip_atomic_store(&touch[t], xp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (done) {
+                        atomicAdd(&vals[h], 1u);
+                    } else {
+                        const u32 old = __hip_atomic_fetch_add(&gc[xp], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        if (old == 0) {
+                            const u32 t = atomicAdd(&s_ntouch, 1u);
+                            __hip_atomic_store(&touch[t], xp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        }
                     }
-                }
                 }
             }
             __syncthreads();
@@ -1091,51 +1117,70 @@ __global__ void k_work_full(const i64 *xrow, const i32 *xadj, const i32 *ydeg, c
 __global__ void k_frontier(unsigned char *st, const u64 *sup, const u64 *w, u64 *init, u64 *wsnap, i32 *part, i64 nx,
                            TipCtl *ctl, i32 pid, int snapshot, i32 *F) {
     const u64 B = ctl->bound;
-    for (i64 x = blockIdx.x * (i64)blockDim.x + threadIdx.x; x < nx; x += (i64)gridDim.x * blockDim.x) {
-        if (st[x] != ST_ALIVE) continue;
-        u64 s = sup[x];
-        if (snapshot) {
-            init[x] = s;
-            wsnap[x] = w[x];
+    const i64 stride = (i64)gridDim.x * blockDim.x;
+    const i64 nn = (nx + WAVE - 1) / WAVE * WAVE;  // wave-uniform trip count
+    for (i64 x = blockIdx.x * (i64)blockDim.x + threadIdx.x; x < nn; x += stride) {
+        bool take = false;
+        if (x < nx && st[x] == ST_ALIVE) {
+            const u64 s = sup[x];
+            if (snapshot) {
+                init[x] = s;
+                wsnap[x] = w[x];
+            }
+            take = s < B;
         }
-        if (s < B) {
+        const u32 p = wave_append(&ctl->nF, take);
+        if (take) {
             st[x] = ST_ACTIVE;
             part[x] = pid;
-            u32 p = atomicAdd(&ctl->nF, 1u);
             F[p] = (i32)x;
         }
     }
 }
 
 // Active vertices become peeled: their Y neighbours lose one live degree and
-// are queued for list compaction.  One wave per vertex.
+// are queued for list compaction (one queue append per wave and step).  One
+// wave per vertex.
 __global__ void k_retire(const i32 *F, const u32 *nF, const i64 *xrow, const i32 *xadj, unsigned char *st, i32 *ydeg,
-                         unsigned char *ydirty, i32 *dirty, u32 *ndirty, const u64 *wsnap, TipCtl *ctl, int dynamic) {
+                         unsigned char *ydirty, i32 *dirty, u32 *ndirty, int dynamic) {
     const int lane = threadIdx.x & (WAVE - 1);
     const i64 wave = (blockIdx.x * (i64)blockDim.x + threadIdx.x) / WAVE;
     const i64 nwaves = (i64)gridDim.x * blockDim.x / WAVE;
     const u32 n = *nF;
     for (i64 i = wave; i < n; i += nwaves) {
-        i32 x = F[i];
-        if (lane == 0) {
-            st[x] = ST_PEELED;
-            atomicAdd((unsigned long long *)&ctl->est_final, (unsigned long long)wsnap[x]);
-        }
-        for (i64 j = xrow[x] + lane; j < xrow[x + 1]; j += WAVE) {
-            i32 y = xadj[j];
-            atomicSub(&ydeg[y], 1);
-            if (dynamic) {
-                // byte flag per y: first setter queues y
-                unsigned int *word = (unsigned int *)(ydirty + (y & ~3));
-                unsigned int bit = 0xFFu << (8 * (y & 3));
-                unsigned int old = atomicOr(word, bit);
-                if ((old & bit) == 0) {
-                    u32 p = atomicAdd(ndirty, 1u);
-                    dirty[p] = y;
+        const i32 x = F[i];
+        if (lane == 0) st[x] = ST_PEELED;
+        const i64 je = xrow[x + 1];
+        for (i64 j0 = xrow[x]; j0 < je; j0 += WAVE) {  // wave-uniform trip count
+            const i64 j = j0 + lane;
+            bool fresh = false;
+            i32 y = 0;
+            if (j < je) {
+                y = xadj[j];
+                atomicSub(&ydeg[y], 1);
+                if (dynamic) {
+                    // byte flag per y: first setter queues y
+                    unsigned int *word = (unsigned int *)(ydirty + (y & ~3));
+                    const unsigned int bit = 0xFFu << (8 * (y & 3));
+                    fresh = (atomicOr(word, bit) & bit) == 0;
                 }
             }
+            const u32 p = wave_append(ndirty, fresh);
+            if (fresh) dirty[p] = y;
         }
     }
+}
+
+// Work of the partition's vertices (all peeled by now), summed for the
+// scaling factor of the next partition; one device atomic per workgroup.
+__global__ __launch_bounds__(256) void k_part_work(const unsigned char *st, const i32 *part, const u64 *wsnap, i64 nx,
+                                                   i32 pid, TipCtl *ctl) {
+    __shared__ u64 red[256 / WAVE];
+    u64 t = 0;
+    for (i64 x = blockIdx.x * (i64)blockDim.x + threadIdx.x; x < nx; x += (i64)gridDim.x * blockDim.x)
+        if (st[x] == ST_PEELED && part[x] == pid) t += wsnap[x];
+    t = block_sum_u64<256>(t, red);
+    if (threadIdx.x == 0 && t) atomicAdd((unsigned long long *)&ctl->est_final, (unsigned long long)t);
 }
 
 __global__ void k_activate(const i32 *F2, const u32 *nF2, unsigned char *st, i32 *part, i32 pid) {
@@ -1148,9 +1193,11 @@ __global__ void k_activate(const i32 *F2, const u32 *nF2, unsigned char *st, i32
 }
 
 // In-place compaction of dirty Y lists to their alive entries; one wave per
-// list, 64 entries per step with a ballot prefix.
+// list, four 64-entry chunks per step (their loads in flight together) with
+// a ballot prefix.
 __global__ void k_compact(const i32 *dirty, const u32 *ndirty, const i64 *yrow, i32 *yadj, i32 *ylen,
                           unsigned char *ydirty, const unsigned char *st) {
+    constexpr int CU = 4;
     const int lane = threadIdx.x & (WAVE - 1);
     const i64 wave = (blockIdx.x * (i64)blockDim.x + threadIdx.x) / WAVE;
     const i64 nwaves = (i64)gridDim.x * blockDim.x / WAVE;
@@ -1161,13 +1208,22 @@ __global__ void k_compact(const i32 *dirty, const u32 *ndirty, const i64 *yrow, 
         const i64 b = yrow[y];
         const i32 len = ylen[y];
         i32 out = 0;
-        for (i32 k0 = 0; k0 < len; k0 += WAVE) {
-            i32 k = k0 + lane;
-            i32 x = k < len ? yadj[b + k] : -1;
-            bool keep = k < len && st[x] == ST_ALIVE;
-            u64 bal = __ballot(keep);
-            if (keep) yadj[b + out + __popcll(bal & lt)] = x;
-            out += __popcll(bal);
+        for (i32 k0 = 0; k0 < len; k0 += CU * WAVE) {
+            i32 xv[CU];
+#pragma unroll
+            for (int c = 0; c < CU; ++c) {
+                const i32 k = k0 + c * WAVE + lane;
+                xv[c] = k < len ? yadj[b + k] : -1;
+            }
+            bool keep[CU];
+#pragma unroll
+            for (int c = 0; c < CU; ++c) keep[c] = xv[c] >= 0 && st[xv[c]] == ST_ALIVE;
+#pragma unroll
+            for (int c = 0; c < CU; ++c) {
+                const u64 bal = __ballot(keep[c]);
+                if (keep[c]) yadj[b + out + __popcll(bal & lt)] = xv[c];
+                out += __popcll(bal);
+            }
         }
         if (lane == 0) {
             ylen[y] = out;
@@ -1922,7 +1978,7 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
             if ((i64)nF == n_alive) {
                 // everything left joins this partition: no updates needed
                 hipLaunchKernelGGL(k_retire, dim3(gw), dim3(256), 0, s, (const i32 *)F, (const u32 *)&ctl->nF, xrow, xadj, st,
-                                   ydeg, ydirty, dirty, &ctl->ndirty, (const u64 *)wsnap, ctl, 0);
+                                   ydeg, ydirty, dirty, &ctl->ndirty, 0);
                 PBNG_LAUNCH_CHECK();
                 n_alive = 0;
                 hipLaunchKernelGGL(k_next_round, dim3(1), dim3(1), 0, s, ctl);
@@ -1931,7 +1987,7 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
             if (batch && hv.wF > wedge_cnt_bound) {
                 // Section 5.1: recount the remaining graph instead of peeling
                 hipLaunchKernelGGL(k_retire, dim3(gw), dim3(256), 0, s, (const i32 *)F, (const u32 *)&ctl->nF, xrow, xadj, st,
-                                   ydeg, ydirty, dirty, &ctl->ndirty, (const u64 *)wsnap, ctl, dynamic ? 1 : 0);
+                                   ydeg, ydirty, dirty, &ctl->ndirty, dynamic ? 1 : 0);
                 hipLaunchKernelGGL(k_alive_label, dim3(grid_1d(G.n)), dim3(256), 0, s, (const unsigned char *)st,
                                    (const i32 *)G.gid, G.n, xoff, nx, alive_label);
                 PBNG_LAUNCH_CHECK();
@@ -2054,7 +2110,7 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
                     trace_t = tnow;
                 }
                 hipLaunchKernelGGL(k_retire, dim3(gw), dim3(256), 0, s, (const i32 *)F, (const u32 *)&ctl->nF, xrow, xadj, st,
-                                   ydeg, ydirty, dirty, &ctl->ndirty, (const u64 *)wsnap, ctl, dynamic ? 1 : 0);
+                                   ydeg, ydirty, dirty, &ctl->ndirty, dynamic ? 1 : 0);
                 hipLaunchKernelGGL(k_activate, dim3(grid_1d(nx)), dim3(256), 0, s, (const i32 *)F2, (const u32 *)&ctl->nF2, st,
                                    part, pid);
                 PBNG_LAUNCH_CHECK();
@@ -2072,6 +2128,8 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
             PBNG_HIP(hipMemcpyAsync(&hv.wF, &ctl->wF, sizeof(u64), hipMemcpyDeviceToHost, s));
             PBNG_HIP(hipStreamSynchronize(s));
         }
+        hipLaunchKernelGGL(k_part_work, dim3(std::min<i64>(grid_1d(nx), 512)), dim3(256), 0, s, (const unsigned char *)st,
+                           (const i32 *)part, (const u64 *)wsnap, nx, pid, ctl);
         hipLaunchKernelGGL(k_scale, dim3(1), dim3(1), 0, s, ctl);
         PBNG_LAUNCH_CHECK();
         ++pid;
