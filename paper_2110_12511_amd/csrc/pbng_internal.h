@@ -162,10 +162,12 @@ void wing_decompose(Ctx &c, const DevGraph &G, const pbng_opts &o, u64 *theta_de
 // Smallest s with sum{w_l : active_l, key_l <= s} >= target; if the total is
 // below target, the largest active key.  Result written to *s_out (device).
 // The target is *target_dev, or, when scale_dev is given, the plain rule's
-// scale * (alive work) / parts_left computed on the device.
+// scale * (alive work) / parts_left computed on the device.  A nonzero
+// count_target also ends the range where #{active_l : key_l <= s} reaches it
+// (s is the smaller of the two crossings).
 void weighted_select(Ctx &c, const u64 *key, const u64 *w, const unsigned char *state,
                      unsigned char alive_code, i64 n, const u64 *target_dev, const double *scale_dev,
-                     int parts_left, u64 *s_out, u64 *work_at_s_out);
+                     int parts_left, u64 *s_out, u64 *work_at_s_out, u64 count_target = 0);
 
 // Counting pass with an optional alive filter by label (recounts).
 // Returns the wedges walked.  sup_label / sup_edge are overwritten.

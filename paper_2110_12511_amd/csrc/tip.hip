@@ -1429,13 +1429,23 @@ __global__ __launch_bounds__(FD_BLOCK) void k_tip_fd(FdArgs a) {
         i64 *const lsup = in_lds ? s_lsup : g_lsup;
         unsigned char *const lst = in_lds ? s_lst : g_lst;
         i32 *const lbatch = in_lds ? s_lbatch : g_lbatch;
-        u64 mn = ~0ull;
-        for (i32 k = threadIdx.x; k < ni; k += BLOCK) {
+        // Thread t owns vertices t, t + BLOCK, ...  Each pass that computes
+        // a level's minimum also records, in a bit mask, which of the
+        // thread's vertices hold the thread's minimum, so the next level's
+        // batch comes from the mask instead of another scan (partitions of
+        // at most 64 * BLOCK vertices; larger ones scan).
+        const bool masked = ni <= 64 * BLOCK;
+        u64 mn = ~0ull, cm = 0;
+        for (i32 k = threadIdx.x, e = 0; k < ni; k += BLOCK, ++e) {
             const u64 v0 = a.init[a.xs[base + k]];
             st_coherent(&lsup[k], (i64)v0);
             st_coherent(&lst[k], (unsigned char)1);
             st_coherent(&lcnt[k], 0u);
-            mn = v0 < mn ? v0 : mn;
+            if (v0 < mn) {
+                mn = v0;
+                cm = 0;
+            }
+            if (v0 == mn && e < 64) cm |= 1ull << e;
         }
         u64 kmin = block_min_u64<BLOCK>(mn, s_red);
         __syncthreads();
@@ -1443,12 +1453,24 @@ __global__ __launch_bounds__(FD_BLOCK) void k_tip_fd(FdArgs a) {
         while (remaining > 0) {
             if (threadIdx.x == 0) s_cnt[0] = s_cnt[2] = 0;
             __syncthreads();
-            for (i32 k = threadIdx.x; k < ni; k += BLOCK) {
-                if (ld_coherent(&lst[k]) == 1 && (u64)ld_coherent(&lsup[k]) == kmin) {
+            if (masked) {
+                u64 bits = mn == kmin ? cm : 0ull;
+                while (bits) {
+                    const i32 k = threadIdx.x + (__ffsll((unsigned long long)bits) - 1) * BLOCK;
+                    bits &= bits - 1;
                     const u32 p = atomicAdd(&s_cnt[0], 1u);
                     st_coherent(&lbatch[p], k);
                     st_coherent(&lst[k], (unsigned char)2);
                     a.theta[a.xs[base + k]] = kmin;
+                }
+            } else {
+                for (i32 k = threadIdx.x; k < ni; k += BLOCK) {
+                    if (ld_coherent(&lst[k]) == 1 && (u64)ld_coherent(&lsup[k]) == kmin) {
+                        const u32 p = atomicAdd(&s_cnt[0], 1u);
+                        st_coherent(&lbatch[p], k);
+                        st_coherent(&lst[k], (unsigned char)2);
+                        a.theta[a.xs[base + k]] = kmin;
+                    }
                 }
             }
             __syncthreads();
@@ -1624,23 +1646,42 @@ __global__ __launch_bounds__(FD_BLOCK) void k_tip_fd(FdArgs a) {
                 }
                 __syncthreads();
             }
-            // clamp at the level, retire the batch and find the next level
-            u64 nmn = ~0ull;
-            for (i32 k = threadIdx.x; k < ni; k += BLOCK) {
-                const unsigned char st = ld_coherent(&lst[k]);
-                if (st == 2) {
-                    st_coherent(&lst[k], (unsigned char)0);
-                } else if (st == 1) {
-                    i64 v = ld_coherent(&lsup[k]);
-                    if (v < (i64)kmin) {
-                        v = (i64)kmin;
-                        st_coherent(&lsup[k], v);
+            // clamp at the level, retire the batch and find the next level;
+            // eight vertices per step with their state and support loads in
+            // flight together
+            mn = ~0ull;
+            cm = 0;
+            for (i32 k0 = threadIdx.x, e0 = 0; k0 < ni; k0 += 8 * BLOCK, e0 += 8) {
+                unsigned char sv[8];
+                i64 vv[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const i32 k = k0 + q * BLOCK;
+                    sv[q] = ld_coherent(&lst[k < ni ? k : 0]);
+                    vv[q] = ld_coherent(&lsup[k < ni ? k : 0]);
+                }
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const i32 k = k0 + q * BLOCK;
+                    if (k >= ni) continue;
+                    if (sv[q] == 2) {
+                        st_coherent(&lst[k], (unsigned char)0);
+                    } else if (sv[q] == 1) {
+                        i64 v = vv[q];
+                        if (v < (i64)kmin) {
+                            v = (i64)kmin;
+                            st_coherent(&lsup[k], v);
+                        }
+                        if ((u64)v < mn) {
+                            mn = (u64)v;
+                            cm = 0;
+                        }
+                        if ((u64)v == mn && e0 + q < 64) cm |= 1ull << (e0 + q);
                     }
-                    nmn = (u64)v < nmn ? (u64)v : nmn;
                 }
             }
             remaining -= nb;
-            kmin = block_min_u64<BLOCK>(nmn, s_red);
+            kmin = block_min_u64<BLOCK>(mn, s_red);
             __syncthreads();
         }
     }
@@ -1959,7 +2000,16 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
                 hipLaunchKernelGGL(k_learned_guard, dim3(1), dim3(1), 0, s, ctl, (const u64 *)rmin);
                 PBNG_LAUNCH_CHECK();
             } else {
-                weighted_select(c, sup, w, st, ST_ALIVE, nx, nullptr, &ctl->scale, P - pid, &ctl->s, &ctl->est_init);
+                // ranges also end at a vertex-count target: a partition of many
+                // light vertices peels one level at a time in the
+                // fine-grained phase, with a pass over its vertices per level,
+                // so its cost grows with (vertices x levels), which the work
+                // estimate does not see; the target keeps such partitions
+                // near the size whose state fits in LDS
+                const u64 cnt_target =
+                    std::max<u64>((u64)FD_LDS_NI, (u64)(2 * n_alive / std::max<i64>(P - pid, 1)));
+                weighted_select(c, sup, w, st, ST_ALIVE, nx, nullptr, &ctl->scale, P - pid, &ctl->s, &ctl->est_init,
+                                cnt_target);
             }
         }
         hipLaunchKernelGGL(k_set_bound, dim3(1), dim3(1), 0, s, ctl, last ? 1 : 0);
