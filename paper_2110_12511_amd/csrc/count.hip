@@ -16,9 +16,9 @@
 //                          counter array over all labels in HBM plus a list of
 //                          the labels it touched
 // Inside a start, the (mid, prefix) segments are processed BLOCK at a time:
-// a block scan of the prefix lengths lets each lane pick its wedges by a
-// binary search over the segment starts, so consecutive lanes read
-// consecutive entries of the same N_mid whatever the degree mix.
+// a block scan of the prefix lengths lets each lane take a run of
+// consecutive wedges, found by one binary search over the segment starts and
+// a forward walk, whatever the degree mix.
 #include "pbng_internal.h"
 
 #include <algorithm>
@@ -79,6 +79,53 @@ struct ChunkSmem {
     i64 *bcast;  // [1]
 };
 
+// Visits the wedges k0 .. k0 + UNR - 1 of a chunk whose segment wedge counts
+// have inclusive prefix pre[0..last] and whose runs start at ladj[moff[l]]:
+// one binary search finds the segment of k0, the rest of the run walks
+// forward (reading the next prefix only where a segment ends), the far ends
+// are loaded together (a wedge past tot reads ladj[0], which exists whenever
+// tot > 0), then fn(seg, pos, far end) runs for each wedge below tot.
+constexpr int CR_UNR = 4;
+template <int UNR, class F>
+__device__ __forceinline__ void chunk_run(const i32 *ladj, const i32 *pre, const i64 *moff, int last, i32 k0, i32 tot,
+                                          F fn) {
+    int sq[UNR];
+    i64 pq[UNR];
+#pragma unroll
+    for (int q = 0; q < UNR; ++q) {
+        sq[q] = -1;
+        pq[q] = 0;
+    }
+    if (k0 < tot) {
+        int l = 0, h = last;
+        while (l < h) {
+            const int md = (l + h) >> 1;
+            if (pre[md] > k0) h = md; else l = md + 1;
+        }
+        i32 end = pre[l];
+        i64 base = moff[l] - (l ? pre[l - 1] : 0);
+#pragma unroll
+        for (int q = 0; q < UNR; ++q) {
+            const i32 k = k0 + q;
+            if (k < tot) {
+                while (k >= end) {
+                    ++l;
+                    base = moff[l] - end;
+                    end = pre[l];
+                }
+                sq[q] = l;
+                pq[q] = base + k;
+            }
+        }
+    }
+    i32 lq[UNR];
+#pragma unroll
+    for (int q = 0; q < UNR; ++q) lq[q] = ladj[pq[q]];
+#pragma unroll
+    for (int q = 0; q < UNR; ++q)
+        if (sq[q] >= 0) fn(sq[q], pq[q], lq[q]);
+}
+
 // Calls wedge(seg, jmid, last, pos) for every wedge of start s, where jmid is
 // the entry of mid in N_s, seg = jmid - chunk base, and pos the entry of last
 // in N_mid; chunk_end(cb) runs after each chunk of BLOCK mids, between
@@ -101,18 +148,12 @@ __device__ __forceinline__ void for_each_wedge(const CountArgs &a, i32 s, const 
         sm.pre[threadIdx.x] = incl;
         sm.moff[threadIdx.x] = moff;
         __syncthreads();
-        for (i32 k = threadIdx.x; k < tot; k += BLOCK) {
-            int lo = 0, hi = BLOCK - 1;  // first seg with pre > k
-            while (lo < hi) {
-                int md = (lo + hi) >> 1;
-                if (sm.pre[md] > k) hi = md; else lo = md + 1;
-            }
-            i32 before = lo ? sm.pre[lo - 1] : 0;
-            i64 pos = sm.moff[lo] + (k - before);
-            i32 last = a.ladj[pos];
-            if (a.alive && !a.alive[last]) continue;
-            wedge(lo, cb + lo, last, pos);
-        }
+        for (i32 kb = 0; kb < tot; kb += CR_UNR * BLOCK)
+            chunk_run<CR_UNR>(a.ladj, sm.pre, sm.moff, BLOCK - 1, kb + (i32)threadIdx.x * CR_UNR, tot,
+                              [&](int seg, i64 pos, i32 last) {
+                                  if (a.alive && !a.alive[last]) return;
+                                  wedge(seg, cb + seg, last, pos);
+                              });
         __syncthreads();
         chunk_end(cb);
         __syncthreads();
@@ -496,18 +537,12 @@ __global__ __launch_bounds__(512) void k_count_tiled(CountArgs a, const u32 *off
                 s_moff[threadIdx.x] = moff;
                 __syncthreads();
                 const int last_seg = (je - cb < BLOCK ? (int)(je - cb) : BLOCK) - 1;
-                for (i32 k = threadIdx.x; k < tot; k += BLOCK) {
-                    int l = 0, h = last_seg;
-                    while (l < h) {
-                        const int md = (l + h) >> 1;
-                        if (s_pre[md] > k) h = md; else l = md + 1;
-                    }
-                    const i32 before = l ? s_pre[l - 1] : 0;
-                    const i64 pos = s_moff[l] + (k - before);
-                    const i32 last = a.ladj[pos];
-                    if (a.alive && !a.alive[last]) continue;
-                    fn(l, cb + l, last, pos);
-                }
+                for (i32 kb = 0; kb < tot; kb += CR_UNR * BLOCK)
+                    chunk_run<CR_UNR>(a.ladj, s_pre, s_moff, last_seg, kb + (i32)threadIdx.x * CR_UNR, tot,
+                                      [&](int seg, i64 pos, i32 last) {
+                                          if (a.alive && !a.alive[last]) return;
+                                          fn(seg, cb + seg, last, pos);
+                                      });
                 __syncthreads();
                 chunk_end(cb);
                 __syncthreads();

@@ -1382,6 +1382,7 @@ constexpr int FD_BLOCK = 512;
 constexpr int FD_LDS_NI = 4096;  // partitions this small live in LDS
 constexpr int FD_WAVE_LOG = 9;                        // per-wave hash slots (log2)
 constexpr int FD_WAVE_W = (1 << FD_WAVE_LOG) * 5 / 8;  // wedges a wave hash takes
+constexpr int FD_UNR = 4;                              // wedges per lane and step
 
 __global__ __launch_bounds__(FD_BLOCK) void k_tip_fd(FdArgs a) {
     constexpr int BLOCK = FD_BLOCK;
@@ -1506,18 +1507,24 @@ __global__ __launch_bounds__(FD_BLOCK) void k_tip_fd(FdArgs a) {
                     s_pre[threadIdx.x] = incl;
                     s_moff[threadIdx.x] = moff;
                     __builtin_amdgcn_wave_barrier();
-                    for (i32 k = lane; k < tot; k += WAVE) {
-                        int lo = 0, hi = WAVE - 1;
-                        while (lo < hi) {
-                            const int md = (lo + hi) >> 1;
-                            if (s_pre[wid * WAVE + md] > k) hi = md; else lo = md + 1;
-                        }
-                        const i32 before = lo ? s_pre[wid * WAVE + lo - 1] : 0;
-                        const i32 xp = a.yps[s_moff[wid * WAVE + lo] + (k - before)];
-                        if (xp == x) continue;
+                    for (i32 kb = 0; kb < tot; kb += FD_UNR * WAVE) {
+                      // far ends, local indices and states of FD_UNR wedges
+                      // are loaded together (every index is inside the
+                      // partition: x itself stands in for wedges past tot)
+                      i32 xq[FD_UNR], kq[FD_UNR];
+                      unsigned char sq[FD_UNR];
+                      run_ends<FD_UNR>(a.yps, s_pre + wid * WAVE, s_moff + wid * WAVE, WAVE - 1, kb + lane * FD_UNR, tot, x,
+                                       xq);
+#pragma unroll
+                      for (int q = 0; q < FD_UNR; ++q) kq[q] = a.loc[xq[q]];
+#pragma unroll
+                      for (int q = 0; q < FD_UNR; ++q) sq[q] = ld_coherent(&lst[kq[q]]);
+#pragma unroll
+                      for (int q = 0; q < FD_UNR; ++q) {
+                        if (xq[q] == x) continue;
                         ++wedges;
-                        const i32 kp = a.loc[xp];
-                        if (ld_coherent(&lst[kp]) != 1) continue;
+                        const i32 kp = kq[q];
+                        if (sq[q] != 1) continue;
                         u32 h = hash32((u32)kp) >> (32 - FD_WAVE_LOG);
                         for (;;) {
                             const i32 kk = hkeys[wid][h];
@@ -1529,6 +1536,7 @@ __global__ __launch_bounds__(FD_BLOCK) void k_tip_fd(FdArgs a) {
                             h = (h + 1) & (HCAP - 1);
                         }
                         atomicAdd(&hvals[wid][h], 1u);
+                      }
                     }
                     __builtin_amdgcn_wave_barrier();
                 }
@@ -1567,19 +1575,21 @@ __global__ __launch_bounds__(FD_BLOCK) void k_tip_fd(FdArgs a) {
                     s_moff[threadIdx.x] = moff;
                     __syncthreads();
                     const int last = (je - cb < BLOCK ? (int)(je - cb) : BLOCK) - 1;
-                    for (i32 k = threadIdx.x; k < tot; k += BLOCK) {
-                        int lo = 0, hi = last;
-                        while (lo < hi) {
-                            const int md = (lo + hi) >> 1;
-                            if (s_pre[md] > k) hi = md; else lo = md + 1;
+                    for (i32 kb = 0; kb < tot; kb += FD_UNR * BLOCK) {
+                        i32 xq[FD_UNR], kq[FD_UNR];
+                        unsigned char sq[FD_UNR];
+                        run_ends<FD_UNR>(a.yps, s_pre, s_moff, last, kb + (i32)threadIdx.x * FD_UNR, tot, x, xq);
+#pragma unroll
+                        for (int q = 0; q < FD_UNR; ++q) kq[q] = a.loc[xq[q]];
+#pragma unroll
+                        for (int q = 0; q < FD_UNR; ++q) sq[q] = ld_coherent(&lst[kq[q]]);
+#pragma unroll
+                        for (int q = 0; q < FD_UNR; ++q) {
+                            if (xq[q] == x) continue;
+                            ++wedges;
+                            if (sq[q] != 1) continue;
+                            atomicAdd(&hmem[kq[q] >> 1], 1u << ((kq[q] & 1) << 4));
                         }
-                        const i32 before = lo ? s_pre[lo - 1] : 0;
-                        const i32 xp = a.yps[s_moff[lo] + (k - before)];
-                        if (xp == x) continue;
-                        ++wedges;
-                        const i32 kp = a.loc[xp];
-                        if (ld_coherent(&lst[kp]) != 1) continue;
-                        atomicAdd(&hmem[kp >> 1], 1u << ((kp & 1) << 4));
                     }
                     __syncthreads();
                 }
@@ -1619,21 +1629,24 @@ __global__ __launch_bounds__(FD_BLOCK) void k_tip_fd(FdArgs a) {
                     s_moff[threadIdx.x] = moff;
                     __syncthreads();
                     const int last = (je - cb < BLOCK ? (int)(je - cb) : BLOCK) - 1;
-                    for (i32 k = threadIdx.x; k < tot; k += BLOCK) {
-                        int lo = 0, hi = last;
-                        while (lo < hi) {
-                            const int md = (lo + hi) >> 1;
-                            if (s_pre[md] > k) hi = md; else lo = md + 1;
-                        }
-                        const i32 before = lo ? s_pre[lo - 1] : 0;
-                        const i32 xp = a.yps[s_moff[lo] + (k - before)];
-                        if (xp == x) continue;
-                        ++wedges;
-                        const i32 kp = a.loc[xp];
-                        if (ld_coherent(&lst[kp]) != 1) continue;
-                        if (atomicAdd(&lcnt[kp], 1u) == 0) {
-                            const u32 t = atomicAdd(&s_cnt[1], 1u);
-                            st_coherent(&ltouch[t], kp);
+                    for (i32 kb = 0; kb < tot; kb += FD_UNR * BLOCK) {
+                        i32 xq[FD_UNR], kq[FD_UNR];
+                        unsigned char sq[FD_UNR];
+                        run_ends<FD_UNR>(a.yps, s_pre, s_moff, last, kb + (i32)threadIdx.x * FD_UNR, tot, x, xq);
+#pragma unroll
+                        for (int q = 0; q < FD_UNR; ++q) kq[q] = a.loc[xq[q]];
+#pragma unroll
+                        for (int q = 0; q < FD_UNR; ++q) sq[q] = ld_coherent(&lst[kq[q]]);
+#pragma unroll
+                        for (int q = 0; q < FD_UNR; ++q) {
+                            if (xq[q] == x) continue;
+                            ++wedges;
+                            if (sq[q] != 1) continue;
+                            const i32 kp = kq[q];
+                            if (atomicAdd(&lcnt[kp], 1u) == 0) {
+                                const u32 t = atomicAdd(&s_cnt[1], 1u);
+                                st_coherent(&ltouch[t], kp);
+                            }
                         }
                     }
                     __syncthreads();
