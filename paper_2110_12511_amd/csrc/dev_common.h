@@ -133,14 +133,12 @@ struct LdsAcc {
         }
     }
     __device__ __forceinline__ void add(i32 key, u32 inc = 1u) {
+        // each probe is one compare-and-swap: it claims an empty slot or
+        // returns the slot's key (one LDS round trip per probe)
         u32 h = hash32((u32)key) >> shift;
         for (;;) {
-            i32 k = keys[h];
-            if (k == key) break;
-            if (k == -1) {
-                i32 prev = atomicCAS(&keys[h], -1, key);
-                if (prev == -1 || prev == key) break;
-            }
+            const i32 prev = atomicCAS(&keys[h], -1, key);
+            if (prev == -1 || prev == key) break;
             h = (h + 1) & mask;
         }
         atomicAdd(&vals[h], inc);
