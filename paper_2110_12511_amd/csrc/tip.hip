@@ -70,6 +70,10 @@ constexpr int H_LOGCAP = 14;
 // active vertices with 2..PAIR_DMAX neighbours whose pairwise list
 // intersections cost less than 1 / PAIR_COST of their wedges take that path
 constexpr i64 PAIR_DMAX = 8;
+// a last range of at most this many alive vertices and at least this much
+// work is peeled one support level per partition (see tip_decompose)
+constexpr i64 LEVEL_MAX_ALIVE = 16384;
+constexpr u64 LEVEL_MIN_WORK = u64(1) << 31;
 constexpr u64 PAIR_COST = 4;
 
 __device__ __forceinline__ int bits_of(u32 v) { return v ? 32 - __clz(v) : 0; }
@@ -1232,6 +1236,25 @@ __global__ void k_compact(const i32 *dirty, const u32 *ndirty, const i64 *yrow, 
     }
 }
 
+// A partition whose range is a single support value k (its bound is the
+// smallest alive support k plus one): every vertex it peels has tip number k
+// (the running maximum of the bottom-up order is k while the cascade below
+// k + 1 runs), so it needs no fine-grained peeling; its level is recorded.
+__global__ void k_level_bound(TipCtl *ctl, const u64 *mn, u64 *plev) {
+    ctl->s = mn[0];
+    *plev = mn[0];
+}
+
+// Work estimate summed over the alive vertices (one device atomic per block).
+__global__ __launch_bounds__(256) void k_alive_work(const unsigned char *st, const u64 *w, i64 nx, u64 *out) {
+    __shared__ u64 red[256 / WAVE];
+    u64 t = 0;
+    for (i64 x = blockIdx.x * (i64)blockDim.x + threadIdx.x; x < nx; x += (i64)gridDim.x * blockDim.x)
+        if (st[x] == ST_ALIVE) t += w[x];
+    t = block_sum_u64<256>(t, red);
+    if (threadIdx.x == 0 && t) atomicAdd((unsigned long long *)out, (unsigned long long)t);
+}
+
 // the learned bound never falls to or below the smallest alive support
 __global__ void k_learned_guard(TipCtl *ctl, const u64 *mn) {
     if (ctl->s < mn[0]) ctl->s = mn[0];
@@ -1355,6 +1378,7 @@ struct FdArgs {
     i32 np;
     u32 *head;
     const u64 *init;
+    const u64 *plev;     // level of a single-value partition, ~0 otherwise
     u64 *theta;
     // per-workgroup scratch, stride maxni
     u64 *lsup;
@@ -1426,6 +1450,12 @@ __global__ __launch_bounds__(FD_BLOCK) void k_tip_fd(FdArgs a) {
         const i32 pid = a.queue[qi];
         const i64 base = a.poff[pid];
         const i32 ni = (i32)(a.poff[pid + 1] - base);
+        const u64 lev = a.plev[pid];
+        if (lev != ~0ull) {
+            // single-value range: every tip number is its level
+            for (i32 k = threadIdx.x; k < ni; k += BLOCK) a.theta[a.xs[base + k]] = lev;
+            continue;
+        }
         const bool in_lds = ni <= FD_LDS_NI;
         i64 *const lsup = in_lds ? s_lsup : g_lsup;
         unsigned char *const lst = in_lds ? s_lst : g_lst;
@@ -1987,13 +2017,52 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
                            huge_w);
         PBNG_LAUNCH_CHECK();
     };
+    // Levels of single-value partitions (~0 for ordinary ranges).  When the
+    // last partition would hold a small, heavy dense core (at most
+    // LEVEL_MAX_ALIVE vertices and LEVEL_MIN_WORK wedges of work or more), its
+    // fine-grained peeling would run on one workgroup; instead the
+    // coarse-grained loop goes on one support level per partition, each
+    // peeled by the whole GPU, and those partitions skip the fine-grained
+    // phase (the partition count then exceeds P).
+    u64 *plev = c.alloc<u64>((i64)P + nx + 1);
+    fill<u64>(c, plev, ~0ull, (i64)P + nx + 1);
+    u64 *alive_work = c.alloc<u64>(1);
+    bool level_mode = false;
+    // the two thresholds can be overridden from the environment (tests use
+    // this to force single-level partitions on small graphs)
+    const char *lv_alive_env = getenv("PBNG_LEVEL_MAX_ALIVE");
+    const char *lv_work_env = getenv("PBNG_LEVEL_MIN_WORK");
+    const i64 level_max_alive = lv_alive_env ? (i64)atoll(lv_alive_env) : LEVEL_MAX_ALIVE;
+    const u64 level_min_work = lv_work_env ? (u64)strtoull(lv_work_env, nullptr, 10) : LEVEL_MIN_WORK;
     while (n_alive > 0) {
-        const bool last = (P - pid) <= 1;
+        const bool at_last = (P - pid) <= 1;
         // work estimate of every alive vertex with the current live degrees
-        hipLaunchKernelGGL(k_work_full, dim3(grid_1d(nx * WAVE)), dim3(256), 0, s, xrow, xadj, (const i32 *)ydeg,
-                           (const unsigned char *)st, nx, w);
-        PBNG_LAUNCH_CHECK();
-        if (!last) {
+        // (not needed once partitions are single levels)
+        if (!level_mode) {
+            hipLaunchKernelGGL(k_work_full, dim3(grid_1d(nx * WAVE)), dim3(256), 0, s, xrow, xadj, (const i32 *)ydeg,
+                               (const unsigned char *)st, nx, w);
+            PBNG_LAUNCH_CHECK();
+        }
+        if (at_last && !level_mode && n_alive <= level_max_alive) {
+            PBNG_HIP(hipMemsetAsync(alive_work, 0, sizeof(u64), s));
+            hipLaunchKernelGGL(k_alive_work, dim3(std::min<i64>(grid_1d(nx), 512)), dim3(256), 0, s,
+                               (const unsigned char *)st, (const u64 *)w, nx, alive_work);
+            PBNG_LAUNCH_CHECK();
+            const u64 wr = read_scalar<u64>(c, alive_work);
+            level_mode = wr >= level_min_work;
+            if (trace)
+                fprintf(stderr, "[pbng-trace] last range: %lld alive, work %llu -> %s\n", (long long)n_alive,
+                        (unsigned long long)wr, level_mode ? "single levels" : "one partition");
+        }
+        const bool last = at_last && !level_mode;
+        if (level_mode) {
+            u64 init2[2] = {~0ull, 0};
+            PBNG_HIP(hipMemcpyAsync(rmin, init2, sizeof(init2), hipMemcpyHostToDevice, s));
+            hipLaunchKernelGGL(k_random_bound, dim3(gx), dim3(256), 0, s, (const u64 *)sup, (const unsigned char *)st, nx,
+                               rmin, rmin + 1);
+            hipLaunchKernelGGL(k_level_bound, dim3(1), dim3(1), 0, s, ctl, (const u64 *)rmin, plev + pid);
+            PBNG_LAUNCH_CHECK();
+        } else if (!last) {
             if (o.bound_rule == PBNG_BOUND_RANDOM) {
                 u64 init2[2] = {~0ull, 0};
                 PBNG_HIP(hipMemcpyAsync(rmin, init2, sizeof(init2), hipMemcpyHostToDevice, s));
@@ -2278,6 +2347,7 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
     fa.head = c.alloc<u32>(1);
     PBNG_HIP(hipMemsetAsync(fa.head, 0, sizeof(u32), s));
     fa.init = init;
+    fa.plev = plev;
     fa.theta = theta;
     fa.maxni = maxni;
     fa.lsup = c.alloc<u64>((i64)fdblocks * maxni);

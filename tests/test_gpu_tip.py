@@ -75,6 +75,38 @@ def test_tip_power_law_partitions(ctx, cl_mid, P):
     assert np.array_equal(gpu_tip(ctx, g, 1, P=P), ev)
 
 
+@pytest.fixture
+def force_levels(monkeypatch):
+    """Forces the last range into single-level partitions whatever its size."""
+    monkeypatch.setenv("PBNG_LEVEL_MAX_ALIVE", str(1 << 40))
+    monkeypatch.setenv("PBNG_LEVEL_MIN_WORK", "0")
+
+
+@pytest.mark.parametrize("P", [1, 3, 40])
+def test_tip_single_level_partitions(ctx, cl_mid, force_levels, P):
+    """A range holding one support value k gives every vertex tip number k
+    with no fine-grained peeling; the last range split that way (here from
+    the first partition on with P = 1) must reproduce the oracle."""
+    g, eu, ev = cl_mid
+    assert np.array_equal(gpu_tip(ctx, g, 0, P=P), eu)
+    if P == 1:
+        # every partition is one level: one partition per distinct tip number
+        assert ctx.stats()["partitions"] == len(np.unique(eu))
+    assert np.array_equal(gpu_tip(ctx, g, 1, P=P), ev)
+
+
+def test_tip_single_level_small_graphs(ctx, force_levels):
+    for s in range(20):
+        rng = np.random.default_rng(300 + s)
+        g = synth.random_small(int(rng.integers(1, 14)), int(rng.integers(1, 10)), float(rng.choice([0.4, 0.8])), seed=s)
+        for side in (0, 1):
+            for P in (1, 2):
+                assert np.array_equal(gpu_tip(ctx, g, side, P=P), oracle.tip(g, side)), (g.name, side, P)
+    for a, b in ((3, 5), (12, 9)):
+        g = synth.complete(a, b)
+        assert np.array_equal(gpu_tip(ctx, g, 0, P=1), oracle.tip(g, 0))
+
+
 @pytest.mark.parametrize("flags", [pb.F_NO_DYNAMIC, pb.F_NO_BATCH, pb.F_NO_DYNAMIC | pb.F_NO_BATCH])
 def test_tip_ablation_flags(ctx, cl_mid, flags):
     g, eu, ev = cl_mid
