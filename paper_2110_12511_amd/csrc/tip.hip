@@ -70,10 +70,12 @@ constexpr int H_LOGCAP = 14;
 // active vertices with 2..PAIR_DMAX neighbours whose pairwise list
 // intersections cost less than 1 / PAIR_COST of their wedges take that path
 constexpr i64 PAIR_DMAX = 8;
-// a last range of at most this many alive vertices and at least this much
-// work is peeled one support level per partition (see tip_decompose)
-constexpr i64 LEVEL_MAX_ALIVE = 16384;
-constexpr u64 LEVEL_MIN_WORK = u64(1) << 31;
+// an alive set of at most this many vertices, with at least this much work
+// in all and per vertex on average, is peeled one support level per
+// partition (see tip_decompose)
+constexpr i64 LEVEL_MAX_ALIVE = 1024;
+constexpr u64 LEVEL_MIN_WORK = u64(1) << 30;
+constexpr u64 LEVEL_MIN_AVG = u64(1) << 21;
 constexpr u64 PAIR_COST = 4;
 
 __device__ __forceinline__ int bits_of(u32 v) { return v ? 32 - __clz(v) : 0; }
@@ -393,7 +395,7 @@ __global__ __launch_bounds__(512) void k_tip_peel_tiled(PeelArgs a, int bin) {
             s_moff[threadIdx.x] = moff;
             __syncthreads();
             const int last = (d - cb < BLOCK ? d - cb : BLOCK) - 1;
-            constexpr int UNR = 8;
+            constexpr int UNR = 6;
             for (i32 kb = 0; kb < tot; kb += UNR * BLOCK) {
                 i32 xq[UNR];
                 run_ends<UNR>(a.yadj, s_pre, s_moff, last, kb + (i32)threadIdx.x * UNR, tot, x, xq);
@@ -2017,13 +2019,13 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
                            huge_w);
         PBNG_LAUNCH_CHECK();
     };
-    // Levels of single-value partitions (~0 for ordinary ranges).  When the
-    // last partition would hold a small, heavy dense core (at most
-    // LEVEL_MAX_ALIVE vertices and LEVEL_MIN_WORK wedges of work or more), its
-    // fine-grained peeling would run on one workgroup; instead the
-    // coarse-grained loop goes on one support level per partition, each
+    // Levels of single-value partitions (~0 for ordinary ranges).  When what
+    // is left is a small, heavy dense core (at most LEVEL_MAX_ALIVE vertices,
+    // LEVEL_MIN_WORK wedges of work or more, LEVEL_MIN_AVG or more per
+    // vertex), its fine-grained peeling would run on one workgroup; instead
+    // the coarse-grained loop goes on one support level per partition, each
     // peeled by the whole GPU, and those partitions skip the fine-grained
-    // phase (the partition count then exceeds P).
+    // phase (the partition count may then exceed P).
     u64 *plev = c.alloc<u64>((i64)P + nx + 1);
     fill<u64>(c, plev, ~0ull, (i64)P + nx + 1);
     u64 *alive_work = c.alloc<u64>(1);
@@ -2034,6 +2036,8 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
     const char *lv_work_env = getenv("PBNG_LEVEL_MIN_WORK");
     const i64 level_max_alive = lv_alive_env ? (i64)atoll(lv_alive_env) : LEVEL_MAX_ALIVE;
     const u64 level_min_work = lv_work_env ? (u64)strtoull(lv_work_env, nullptr, 10) : LEVEL_MIN_WORK;
+    const char *lv_avg_env = getenv("PBNG_LEVEL_MIN_AVG");
+    const u64 level_min_avg = lv_avg_env ? (u64)strtoull(lv_avg_env, nullptr, 10) : LEVEL_MIN_AVG;
     while (n_alive > 0) {
         const bool at_last = (P - pid) <= 1;
         // work estimate of every alive vertex with the current live degrees
@@ -2043,16 +2047,16 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
                                (const unsigned char *)st, nx, w);
             PBNG_LAUNCH_CHECK();
         }
-        if (at_last && !level_mode && n_alive <= level_max_alive) {
+        if (!level_mode && n_alive <= level_max_alive) {
             PBNG_HIP(hipMemsetAsync(alive_work, 0, sizeof(u64), s));
             hipLaunchKernelGGL(k_alive_work, dim3(std::min<i64>(grid_1d(nx), 512)), dim3(256), 0, s,
                                (const unsigned char *)st, (const u64 *)w, nx, alive_work);
             PBNG_LAUNCH_CHECK();
             const u64 wr = read_scalar<u64>(c, alive_work);
-            level_mode = wr >= level_min_work;
+            level_mode = wr >= level_min_work && wr / (u64)n_alive >= level_min_avg;
             if (trace)
-                fprintf(stderr, "[pbng-trace] last range: %lld alive, work %llu -> %s\n", (long long)n_alive,
-                        (unsigned long long)wr, level_mode ? "single levels" : "one partition");
+                fprintf(stderr, "[pbng-trace] partition %d: %lld alive, work %llu -> %s\n", pid, (long long)n_alive,
+                        (unsigned long long)wr, level_mode ? "single levels" : "ranges");
         }
         const bool last = at_last && !level_mode;
         if (level_mode) {

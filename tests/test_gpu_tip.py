@@ -77,16 +77,22 @@ def test_tip_power_law_partitions(ctx, cl_mid, P):
 
 @pytest.fixture
 def force_levels(monkeypatch):
-    """Forces the last range into single-level partitions whatever its size."""
-    monkeypatch.setenv("PBNG_LEVEL_MAX_ALIVE", str(1 << 40))
-    monkeypatch.setenv("PBNG_LEVEL_MIN_WORK", "0")
+    """Single-level partitions as soon as at most `max_alive` vertices are
+    left, whatever their work (the default needs a small, heavy core)."""
+    def setup(max_alive=1 << 40):
+        monkeypatch.setenv("PBNG_LEVEL_MAX_ALIVE", str(max_alive))
+        monkeypatch.setenv("PBNG_LEVEL_MIN_WORK", "0")
+        monkeypatch.setenv("PBNG_LEVEL_MIN_AVG", "0")
+    return setup
 
 
-@pytest.mark.parametrize("P", [1, 3, 40])
-def test_tip_single_level_partitions(ctx, cl_mid, force_levels, P):
+@pytest.mark.parametrize("P,max_alive", [(1, 1 << 40), (40, 5000), (150, 800)])
+def test_tip_single_level_partitions(ctx, cl_mid, force_levels, P, max_alive):
     """A range holding one support value k gives every vertex tip number k
-    with no fine-grained peeling; the last range split that way (here from
-    the first partition on with P = 1) must reproduce the oracle."""
+    with no fine-grained peeling; ranges first, then single levels once few
+    vertices are left (from the start with P = 1), must reproduce the
+    oracle."""
+    force_levels(max_alive)
     g, eu, ev = cl_mid
     assert np.array_equal(gpu_tip(ctx, g, 0, P=P), eu)
     if P == 1:
@@ -96,6 +102,7 @@ def test_tip_single_level_partitions(ctx, cl_mid, force_levels, P):
 
 
 def test_tip_single_level_small_graphs(ctx, force_levels):
+    force_levels()
     for s in range(20):
         rng = np.random.default_rng(300 + s)
         g = synth.random_small(int(rng.integers(1, 14)), int(rng.integers(1, 10)), float(rng.choice([0.4, 0.8])), seed=s)
