@@ -148,7 +148,9 @@ typedef struct {
     uint64_t blooms, bloom_pairs; /* BE-Index size (wing)                    */
     uint64_t rho;             /* coarse-grained peeling rounds (syncs)       */
     uint64_t recounts;        /* tip rounds done by recounting (Section 5.1) */
-    int32_t partitions;       /* partitions actually created                 */
+    int32_t partitions;       /* partitions actually created; tip may exceed
+                                 P when a small heavy core is peeled one
+                                 support level per partition               */
     int32_t P_used;           /* partitions requested after clamping         */
     int32_t bound_rule_used;  /* pbng_bound_rule the call actually used      */
     int32_t fd_wide;          /* wing: partitions peeled by device-wide
