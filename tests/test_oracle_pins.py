@@ -251,3 +251,38 @@ def test_wing_invariants(seed):
         dv = a.sum(axis=0)
         sup = aata[u[keep], v[keep]] - du[u[keep]] - dv[v[keep]] + 1
         assert (sup >= k).all(), k
+
+
+def test_single_level_ranges_give_their_level():
+    """A range holding one support value (the GPU path's single-level
+    partitions): with k the smallest support among the alive vertices of one
+    side, removing every vertex whose support over the remaining graph is
+    at most k, until none is left, must give each removed vertex tip number
+    k.  Supports are recomputed from common-neighbour counts, independently
+    of the oracle."""
+    graphs = _tiny_graphs(40, 700) + [synth.complete(3, 4), synth.complete(4, 6)]
+    for g in graphs:
+        a = _adj(g)
+        for side in (0, 1):
+            m = a if side == 0 else a.T
+            cn = m @ m.T
+            n = m.shape[0]
+            alive = np.ones(n, dtype=bool)
+            theta = np.zeros(n, dtype=np.uint64)
+
+            def supports():
+                c = cn * alive[None, :] * alive[:, None]
+                np.fill_diagonal(c, 0)
+                return (c * (c - 1) // 2).sum(axis=1)
+
+            while alive.any():
+                s = supports()
+                k = int(s[alive].min())
+                while True:
+                    low = alive & (s <= k)
+                    if not low.any():
+                        break
+                    theta[low] = k
+                    alive &= ~low
+                    s = supports()
+            assert np.array_equal(theta, oracle.tip(g, side)), (g.name, side)
