@@ -453,7 +453,7 @@ __global__ __launch_bounds__(512) void k_tip_peel_tiled(PeelArgs a, int bin) {
 // R_x = 1).  A key whose probe sequence is full goes, for every occurrence,
 // to the workgroup's HBM counters with a touched list, so every key lives
 // wholly in one of the two and the result is exact for any key skew.
-constexpr i64 H_RANGE_W = 10240;
+constexpr i64 H_RANGE_W = 8192;
 constexpr u32 H_RANGE_MAX = 64;
 constexpr int H_PROBE = 64;
 
