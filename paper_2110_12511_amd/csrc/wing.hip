@@ -79,24 +79,11 @@ __global__ void w_frontier(unsigned char *st, const u64 *sup, u64 *init, i32 *pa
     }
 }
 
-// Support decrement of an alive edge.  Fire-and-forget (no returned value
-// to wait for): the next active set is found after the round by w_sweep, as
-// every alive edge whose support fell below the bound — the same set that
-// detecting each crossing would give, since alive edges start every round at
-// or above the bound.
-__device__ __forceinline__ void w_dec(u64 *sup, i32 e, u64 d) {
-    atomicAdd((unsigned long long *)&sup[e], (unsigned long long)(0ull - d));
-}
-
-// next active set of a round: alive edges below the bound
-__global__ void w_sweep(const unsigned char *st, const u64 *sup, WingCtl *ctl, i64 m, i32 *F2) {
-    const u64 B = ctl->bound;
-    const i64 stride = (i64)gridDim.x * blockDim.x;
-    const i64 nn = (m + WAVE - 1) / WAVE * WAVE;  // wave-uniform trip count
-    for (i64 e = blockIdx.x * (i64)blockDim.x + threadIdx.x; e < nn; e += stride) {
-        const bool take = e < m && st[e] == WS_ALIVE && sup[e] < B;
-        const u32 p = wave_append(&ctl->nF2, take);
-        if (take) F2[p] = (i32)e;
+__device__ __forceinline__ void w_dec(u64 *sup, i32 e, u64 d, u64 B, i32 *F2, u32 *nF2) {
+    const u64 old = atomicAdd((unsigned long long *)&sup[e], (unsigned long long)(0ull - d));
+    if (old >= B && old - d < B) {
+        u32 p = atomicAdd(nF2, 1u);
+        F2[p] = e;
     }
 }
 
@@ -124,7 +111,7 @@ __global__ void w_links(const i32 *F, const u32 *nF, const i64 *eoff, const i32 
                 const u32 kb = bk[b];
                 const u64 d = kb > 1 ? (u64)kb - 1 : 0;
                 if (d) {
-                    w_dec(sup, et, d);
+                    w_dec(sup, et, d, B, F2, &ctl->nF2);
                     ++upd;
                 }
             }
@@ -174,8 +161,8 @@ __global__ void w_blooms(const i32 *touched, const u32 *ntouch, const i64 *boff,
                 t.wedges += 2;
             }
             if (keep) {
-                w_dec(sup, e1, cnt);
-                w_dec(sup, e2, cnt);
+                w_dec(sup, e1, cnt, B, F2, &ctl->nF2);
+                w_dec(sup, e2, cnt, B, F2, &ctl->nF2);
                 upd += 2;
             }
             if (dynamic) {
@@ -938,8 +925,6 @@ void wing_decompose(Ctx &c, const DevGraph &G, const pbng_opts &o, u64 *theta) {
         hipLaunchKernelGGL(w_blooms, dim3(gfix), dim3(256), 0, rs, (const i32 *)touched, (const u32 *)&ctl->ntouch,
                            (const i64 *)I.boff, blen, bk, bcount, cedge, (const unsigned char *)st, sup, ctl, Fb,
                            dynamic ? 1 : 0, c.kctr + PBNG_K_WING_CD);
-        hipLaunchKernelGGL(w_sweep, dim3(std::min(gm, c.num_cu * 8)), dim3(256), 0, rs, (const unsigned char *)st,
-                           (const u64 *)sup, ctl, m, Fb);
         hipLaunchKernelGGL(w_retire, dim3(c.num_cu * 2), dim3(256), 0, rs, (const i32 *)Fa, (const u32 *)&ctl->nF, st,
                            (const u64 *)init, ctl);
         hipLaunchKernelGGL(w_activate, dim3(c.num_cu * 2), dim3(256), 0, rs, (const i32 *)Fb, (const u32 *)&ctl->nF2, st,
@@ -1030,8 +1015,6 @@ void wing_decompose(Ctx &c, const DevGraph &G, const pbng_opts &o, u64 *theta) {
                                    c.kctr + PBNG_K_WING_CD);
                 c.kend(PBNG_K_WING_CD);
                 PBNG_LAUNCH_CHECK();
-                hipLaunchKernelGGL(w_sweep, dim3(std::min(gm, c.num_cu * 8)), dim3(256), 0, s, (const unsigned char *)st,
-                                   (const u64 *)sup, ctl, m, F2);
                 hipLaunchKernelGGL(w_retire, dim3(grid_1d(nF)), dim3(256), 0, s, (const i32 *)F, (const u32 *)&ctl->nF, st,
                                    (const u64 *)init, ctl);
                 hipLaunchKernelGGL(w_activate, dim3(gm), dim3(256), 0, s, (const i32 *)F2, (const u32 *)&ctl->nF2, st, part,
