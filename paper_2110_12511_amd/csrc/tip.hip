@@ -2030,7 +2030,7 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
     fill<u64>(c, plev, ~0ull, (i64)P + nx + 1);
     u64 *alive_work = c.alloc<u64>(1);
     bool level_mode = false;
-    // the two thresholds can be overridden from the environment (tests use
+    // the three thresholds can be overridden from the environment (tests use
     // this to force single-level partitions on small graphs)
     const char *lv_alive_env = getenv("PBNG_LEVEL_MAX_ALIVE");
     const char *lv_work_env = getenv("PBNG_LEVEL_MIN_WORK");
