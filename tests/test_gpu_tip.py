@@ -114,6 +114,17 @@ def test_tip_single_level_small_graphs(ctx, force_levels):
         assert np.array_equal(gpu_tip(ctx, g, 0, P=1), oracle.tip(g, 0))
 
 
+@pytest.mark.parametrize("min_f", [0, 200])
+def test_tip_receiving_side_rounds(ctx, cl_mid, monkeypatch, min_f):
+    """Rounds peeled from the receiving side (off by default; on for every
+    round at min_f = 0, for active sets of 200 or more at min_f = 200) give
+    the oracle's numbers."""
+    monkeypatch.setenv("PBNG_PULL_MIN_F", str(min_f))
+    g, eu, ev = cl_mid
+    assert np.array_equal(gpu_tip(ctx, g, 0, P=40), eu)
+    assert np.array_equal(gpu_tip(ctx, g, 1, P=40), ev)
+
+
 @pytest.mark.parametrize("flags", [pb.F_NO_DYNAMIC, pb.F_NO_BATCH, pb.F_NO_DYNAMIC | pb.F_NO_BATCH])
 def test_tip_ablation_flags(ctx, cl_mid, flags):
     g, eu, ev = cl_mid
