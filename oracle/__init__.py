@@ -39,7 +39,7 @@ def build(force: bool = True) -> str:
     """Compile oracle.c into liboracle.so (gcc, -O2)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-shared", "-fPIC", "-o", tmp, _SRC])
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-fopenmp", "-shared", "-fPIC", "-o", tmp, _SRC])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -57,7 +57,8 @@ def _load():
     lib.orc_count_edge.argtypes = [i64, i64, _i64p, _i32p, _u64p]
     lib.orc_tip.argtypes = [i64, i64, _i64p, _i32p, i32, _u64p, _u64p, ctypes.c_uint64, ctypes.c_void_p]
     lib.orc_wing.argtypes = [i64, i64, _i64p, _i32p, _u64p, _u64p, ctypes.c_uint64, ctypes.c_void_p]
-    for f in (lib.orc_validate, lib.orc_count_vertex, lib.orc_count_edge, lib.orc_tip, lib.orc_wing):
+    lib.orc_set_threads.argtypes = [i32]
+    for f in (lib.orc_validate, lib.orc_count_vertex, lib.orc_count_edge, lib.orc_tip, lib.orc_wing, lib.orc_set_threads):
         f.restype = i32
     _lib = lib
     return lib
@@ -70,6 +71,12 @@ def _csr(g):
 
 def _ptr(a):
     return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def set_threads(n: int) -> int:
+    """Host threads for counting (start vertices split among them; results
+    do not depend on it).  Peeling stays sequential.  Default 1."""
+    return _load().orc_set_threads(int(n))
 
 
 def validate(g) -> int:

@@ -6,10 +6,14 @@
  * calls this file; only the test-suite, the smoke check and the CPU-baseline
  * leg of the benchmark do.  It shares no code with the HIP library.
  *
- * Everything here is sequential, plain and slow on purpose: each routine is
- * the textbook definition or the paper's sequential bottom-up peeling
+ * Everything here is plain and slow on purpose: each routine is the
+ * textbook definition or the paper's sequential bottom-up peeling
  * (Section 2.2, Algorithm 2), with none of PBNG's two-phase machinery,
- * priority relabelling or BE-Index.
+ * priority relabelling or BE-Index.  Peeling is sequential.  The counting
+ * definitions of Section 2.1 are independent per start vertex, so counting
+ * may hand whole start vertices to several host threads (orc_set_threads;
+ * one thread by default): each start's sums are still formed by one thread
+ * in the same order, so the results do not depend on the thread count.
  *
  * Graph input: U-side CSR.  row_ptr[n_u+1] (int64), col[m] (int32) with the
  * V ids of every row strictly increasing.  Edge id = CSR slot.
@@ -18,6 +22,7 @@
  * Return codes: 0 ok, -1 bad argument, -2 malformed graph, -3 out of memory,
  * -9 stopped early on the work budget (outputs partial).
  */
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -82,47 +87,69 @@ static int transpose(i64 n_u, i64 n_v, const i64 *row_ptr, const i32 *col,
 
 static u64 choose2(u64 c) { return c * (c - 1) / 2; }
 
+/* Host threads used by counting (start vertices split among them). */
+static int g_threads = 1;
+
+int orc_set_threads(int n)
+{
+    g_threads = n > 0 ? n : 1;
+    return g_threads;
+}
+
 /* Per-vertex supports of the rows of a CSR (the "left" side), using the
  * transposed lists for the 2-hop walk.                                     */
 static int count_left(i64 n_l, const i64 *lptr, const i32 *ladj,
                       const i64 *rptr, const i32 *radj, u64 *out_vertex,
                       u64 *out_edge /* optional, indexed by left CSR slot */)
 {
-    u64 *cnt = calloc((size_t)(n_l ? n_l : 1), sizeof(u64));
-    i32 *touched = malloc((size_t)(n_l ? n_l : 1) * sizeof(i32));
-    if (!cnt || !touched) { free(cnt); free(touched); return -3; }
-    for (i64 u = 0; u < n_l; ++u) {
-        i64 nt = 0;
-        for (i64 j = lptr[u]; j < lptr[u + 1]; ++j) {
-            i32 v = ladj[j];
-            for (i64 k = rptr[v]; k < rptr[v + 1]; ++k) {
-                i32 w = radj[k];
-                if (w == u) continue;
-                if (cnt[w] == 0) touched[nt++] = w;
-                cnt[w]++;
-            }
+    int rc = 0;
+#pragma omp parallel num_threads(g_threads)
+    {
+        /* each thread: its own counter array and touched list */
+        u64 *cnt = calloc((size_t)(n_l ? n_l : 1), sizeof(u64));
+        i32 *touched = malloc((size_t)(n_l ? n_l : 1) * sizeof(i32));
+        if (!cnt || !touched) {
+#pragma omp atomic write
+            rc = -3;
         }
-        if (out_vertex) {
-            u64 s = 0;
-            for (i64 t = 0; t < nt; ++t) s += choose2(cnt[touched[t]]);
-            out_vertex[u] = s;
-        }
-        if (out_edge) {
-            for (i64 j = lptr[u]; j < lptr[u + 1]; ++j) {
-                i32 v = ladj[j];
-                u64 s = 0;
-                for (i64 k = rptr[v]; k < rptr[v + 1]; ++k) {
-                    i32 w = radj[k];
-                    if (w == u) continue;
-                    s += cnt[w] - 1;
+#pragma omp barrier
+        if (rc == 0) {
+#pragma omp for schedule(dynamic, 64)
+            for (i64 u = 0; u < n_l; ++u) {
+                i64 nt = 0;
+                for (i64 j = lptr[u]; j < lptr[u + 1]; ++j) {
+                    i32 v = ladj[j];
+                    for (i64 k = rptr[v]; k < rptr[v + 1]; ++k) {
+                        i32 w = radj[k];
+                        if (w == u) continue;
+                        if (cnt[w] == 0) touched[nt++] = w;
+                        cnt[w]++;
+                    }
                 }
-                out_edge[j] = s;
+                if (out_vertex) {
+                    u64 s = 0;
+                    for (i64 t = 0; t < nt; ++t) s += choose2(cnt[touched[t]]);
+                    out_vertex[u] = s;
+                }
+                if (out_edge) {
+                    for (i64 j = lptr[u]; j < lptr[u + 1]; ++j) {
+                        i32 v = ladj[j];
+                        u64 s = 0;
+                        for (i64 k = rptr[v]; k < rptr[v + 1]; ++k) {
+                            i32 w = radj[k];
+                            if (w == u) continue;
+                            s += cnt[w] - 1;
+                        }
+                        out_edge[j] = s;
+                    }
+                }
+                for (i64 t = 0; t < nt; ++t) cnt[touched[t]] = 0;
             }
         }
-        for (i64 t = 0; t < nt; ++t) cnt[touched[t]] = 0;
+        free(cnt);
+        free(touched);
     }
-    free(cnt); free(touched);
-    return 0;
+    return rc;
 }
 
 /* Per-vertex butterfly counts of both sides: out_u[n_u], out_v[n_v]

@@ -6,8 +6,10 @@ the SHA-256 of the uint64 result vector (little-endian, entity order), its
 length, sum and maximum, and a fixed sample of (index, value) pairs, plus the
 oracle's own work counters and wall time.
 
-Usage:  python tests/golden/make_golden.py WORKLOAD QUANTITY
+Usage:  python tests/golden/make_golden.py WORKLOAD QUANTITY [THREADS]
         QUANTITY in {count_u, count_v, count_e, tip_u, tip_v, wing}
+        THREADS: host threads for the oracle's counting (default 1; peeling
+        is sequential either way, and results do not depend on it)
 """
 import hashlib
 import json
@@ -35,8 +37,9 @@ def sample_idx(n: int, k: int = 64, seed: int = 12345) -> np.ndarray:
     return np.unique(rng.integers(0, n, size=min(k, n)))
 
 
-def main(workload: str, quantity: str):
+def main(workload: str, quantity: str, threads: int = 1):
     g = synth.config_graph(workload)
+    oracle.set_threads(threads)
     t0 = time.perf_counter()
     stats = {}
     if quantity == "count_u":
@@ -63,6 +66,7 @@ def main(workload: str, quantity: str):
         max=str(int(res.max())) if res.size else "0",
         sample=[[int(i), str(int(res[i]))] for i in idx],
         oracle_seconds=round(dt, 3),
+        oracle_count_threads=threads,
         oracle_stats={k: v for k, v in stats.items() if k != "seconds"},
     )
     path = os.path.join(HERE, f"{workload}__{quantity}.json")
@@ -72,4 +76,4 @@ def main(workload: str, quantity: str):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1], sys.argv[2])
+    main(sys.argv[1], sys.argv[2], int(sys.argv[3]) if len(sys.argv) > 3 else 1)
