@@ -72,10 +72,17 @@ typedef enum { PBNG_SIDE_U = 0, PBNG_SIDE_V = 1 } pbng_side;
  * shape the schedule; results are identical under every rule.             */
 typedef enum {
     PBNG_BOUND_PLAIN = 0,   /* the paper's work-estimate rule with adaptive
-                               target and scaling factor                    */
+                               target and scaling factor; tip ranges also
+                               end at a vertex-count target, and a small
+                               heavy core is peeled one level per partition */
     PBNG_BOUND_LEARNED = 1, /* predicted entity numbers from a loaded MLP;
                                the plain rule when no predictor is loaded   */
-    PBNG_BOUND_RANDOM = 2   /* seeded random increasing bounds (tests)      */
+    PBNG_BOUND_RANDOM = 2,  /* seeded random increasing bounds (tests)      */
+    PBNG_BOUND_PAPER = 3    /* the paper's rule alone (Section 3.1.3): tip
+                               ranges end at the work crossing only, with
+                               neither the library's vertex-count target nor
+                               its single-level partitions (PLAIN has both;
+                               wing is the same under both rules)          */
 } pbng_bound_rule;
 
 /* flags */
@@ -134,6 +141,19 @@ typedef struct {
     int32_t wide_work;  /* wing: fine-grained work above which a partition
                            is peeled by device-wide kernels; 0 = library
                            default (2^24), negative = never (schedule only)  */
+    int32_t level_alive;/* tip: coarse-grained partitions of one support
+                           level each (they need no fine-grained peeling)
+                           once at most this many vertices are alive; 0 =
+                           library default (1024 vertices holding at least
+                           2^30 wedges of work, 2^21 per vertex), positive =
+                           at that count whatever the work, negative = never
+                           (schedule only)                                  */
+    int32_t recount_w;  /* tip: a coarse-grained round recounts the remaining
+                           graph instead of peeling when its active set's
+                           live wedges exceed this (Section 5.1); 0 = the
+                           paper's bound, the sum over edges of
+                           min(d_u, d_v) in the input graph; negative = never
+                           (schedule only)                                  */
 } pbng_opts;
 
 /* Per-call counters and phase times of the last compute call. */
@@ -176,6 +196,29 @@ int pbng_count(pbng_ctx *ctx, const pbng_csr *g, pbng_count_kind kind,
  * [n_u] for PBNG_SIDE_U, [n_v] for PBNG_SIDE_V.  opts may be NULL.       */
 int pbng_tip(pbng_ctx *ctx, const pbng_csr *g, pbng_side side,
              const pbng_opts *opts, uint64_t *tip_out);
+
+/* Tip numbers plus the coarse-grained schedule that produced them (Section
+ * 3.1, Algorithm 4; Theorem 1 states what it must satisfy).  Outputs, all in
+ * the graph's memory space:
+ *   tip_out    uint64[n_side]  tip numbers, as pbng_tip;
+ *   part_out   int32[n_side]   partition of each vertex (0-based; the
+ *                              partition during which it was peeled);
+ *   init_out   uint64[n_side]  its support when its partition began, i.e.
+ *                              its butterflies inside the vertices of its own
+ *                              and later partitions (the initialisation
+ *                              vector of the fine-grained phase);
+ *   bounds_out uint64[bounds_cap]  exclusive upper bound theta(i+1) of
+ *                              partition i for i < min(partitions, cap)
+ *                              (UINT64_MAX for a final partition that takes
+ *                              every remaining vertex);
+ *   *nparts    number of partitions created (may exceed bounds_cap).
+ * By Theorem 1 every vertex of partition i has theta(i) <= tip < theta(i+1)
+ * with theta(0) = 0.  bounds_out may be NULL when bounds_cap is 0.        */
+int pbng_tip_schedule(pbng_ctx *ctx, const pbng_csr *g, pbng_side side,
+                      const pbng_opts *opts, uint64_t *tip_out,
+                      int32_t *part_out, uint64_t *init_out,
+                      uint64_t *bounds_out, int32_t bounds_cap,
+                      int32_t *nparts);
 
 /* Wing numbers of every edge (Definition 1; Section 3.3, Algorithms 4-6).
  * wing_out: uint64[m].  opts may be NULL.                                 */
@@ -250,6 +293,12 @@ int pbng_autotune(pbng_ctx *ctx, const pbng_csr *g, int32_t kind,
  * same memory space as the graph.                                          */
 int pbng_tip_features(pbng_ctx *ctx, const pbng_csr *g, pbng_side side,
                       float *feat);
+/* Load predictor parameters from a file: a NumPy .npy array of
+ * PBNG_MLP_NPARAM little-endian float32 values (version 1 or 2 header, C
+ * order), in the layout above; Adam state cleared.  PBNG_E_ARG for a
+ * missing or malformed file (the context then keeps its previous
+ * parameters; without any, PBNG_BOUND_LEARNED runs the plain rule).        */
+int pbng_predictor_load(pbng_ctx *ctx, const char *path);
 /* He-uniform weights and zero biases from a seed; Adam state cleared.     */
 int pbng_mlp_init(pbng_ctx *ctx, uint64_t seed);
 /* Copy parameters in from / out to host memory (PBNG_MLP_NPARAM floats);

@@ -13,6 +13,7 @@ from .binding import (  # noqa: F401
     BOUND_PLAIN,
     BOUND_LEARNED,
     BOUND_RANDOM,
+    BOUND_PAPER,
     F_NO_BATCH,
     F_NO_DENSE_TILE,
     F_NO_DYNAMIC,
@@ -25,6 +26,7 @@ from .binding import (  # noqa: F401
     make_opts,
     tip,
     tip_batch,
+    tip_schedule,
     tip_features,
     wing_batch,
     to_numpy_u64,

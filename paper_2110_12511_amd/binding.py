@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libpbng.so")
 
 COUNT_VERTEX_U, COUNT_VERTEX_V, COUNT_EDGE = 0, 1, 2
 SIDE_U, SIDE_V = 0, 1
-BOUND_PLAIN, BOUND_LEARNED, BOUND_RANDOM = 0, 1, 2
+BOUND_PLAIN, BOUND_LEARNED, BOUND_RANDOM, BOUND_PAPER = 0, 1, 2, 3
 F_NO_DYNAMIC, F_NO_BATCH, F_NO_DENSE_TILE = 0x1, 0x2, 0x4
 
 ERRORS = {
@@ -57,6 +57,8 @@ class Opts(ctypes.Structure):
         ("tile_w", ctypes.c_int32),
         ("batch_edges", ctypes.c_int32),
         ("wide_work", ctypes.c_int32),
+        ("level_alive", ctypes.c_int32),
+        ("recount_w", ctypes.c_int32),
     ]
 
 
@@ -115,7 +117,8 @@ class Stats(ctypes.Structure):
 
 EXPORTS = ["pbng_create", "pbng_destroy", "pbng_last_error", "pbng_last_stats", "pbng_count", "pbng_tip", "pbng_wing",
            "pbng_tip_features", "pbng_mlp_init", "pbng_mlp_set", "pbng_mlp_get", "pbng_mlp_forward",
-           "pbng_mlp_loss_grad", "pbng_mlp_train", "pbng_tip_batch", "pbng_wing_batch", "pbng_autotune"]
+           "pbng_mlp_loss_grad", "pbng_mlp_train", "pbng_tip_batch", "pbng_wing_batch", "pbng_autotune",
+           "pbng_tip_schedule", "pbng_predictor_load"]
 MLP_NPARAM = 8961
 
 _lib = None
@@ -162,6 +165,9 @@ def load():
         "pbng_wing_batch": [vp, vp, ctypes.c_int32, ctypes.POINTER(Opts), vp],
         "pbng_autotune": [vp, ctypes.POINTER(Csr), ctypes.c_int32, ctypes.POINTER(Opts), ctypes.POINTER(Opts),
                           ctypes.POINTER(ctypes.c_double)],
+        "pbng_tip_schedule": [vp, ctypes.POINTER(Csr), ctypes.c_int, ctypes.POINTER(Opts), vp, vp, vp, vp,
+                              ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
+        "pbng_predictor_load": [vp, ctypes.c_char_p],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -172,10 +178,11 @@ def load():
 
 
 def make_opts(P=0, bound_rule=BOUND_PLAIN, flags=0, seed=0, dense_cut=0, tile_w=0, batch_edges=0,
-              wide_work=0) -> Opts:
+              wide_work=0, level_alive=0, recount_w=0) -> Opts:
     o = Opts()
     o.P, o.bound_rule, o.flags, o.seed, o.dense_cut = int(P), int(bound_rule), int(flags), int(seed), int(dense_cut)
     o.tile_w, o.batch_edges, o.wide_work = int(tile_w), int(batch_edges), int(wide_work)
+    o.level_alive, o.recount_w = int(level_alive), int(recount_w)
     return o
 
 
@@ -232,6 +239,10 @@ class Context:
         return best, float(ms.value)
 
     # learned range-bound predictor ----------------------------------------
+    def predictor_load(self, path: str):
+        """Load predictor parameters from a .npy file of MLP_NPARAM float32."""
+        self._check(self.lib.pbng_predictor_load(self.h, os.fsencode(path)))
+
     def mlp_init(self, seed: int = 0):
         self._check(self.lib.pbng_mlp_init(self.h, ctypes.c_uint64(int(seed))))
 
@@ -326,6 +337,25 @@ def tip(ctx: Context, dg: DeviceGraph, side: int, opts: Opts | None = None):
     out = _out_tensor(n)
     ctx.tip_raw(dg.csr(), side, out.data_ptr(), opts)
     return out[:n]
+
+
+def tip_schedule(ctx: Context, dg: DeviceGraph, side: int, opts: Opts | None = None, bounds_cap: int = 1 << 16):
+    """(tip numbers, partition ids, supports at partition start, partition
+    upper bounds) of one side, as uint64 / int32 device tensors."""
+    import torch
+
+    n = dg.n_u if side == SIDE_U else dg.n_v
+    tip_t = _out_tensor(n)
+    part = torch.zeros(max(n, 1), dtype=torch.int32, device="cuda")
+    init = _out_tensor(n)
+    bounds = _out_tensor(bounds_cap)
+    np_out = ctypes.c_int32()
+    ctx._check(ctx.lib.pbng_tip_schedule(ctx.h, ctypes.byref(dg.csr()), side, ctypes.byref(opts) if opts else None,
+                                         ctypes.c_void_p(tip_t.data_ptr()), ctypes.c_void_p(part.data_ptr()),
+                                         ctypes.c_void_p(init.data_ptr()), ctypes.c_void_p(bounds.data_ptr()),
+                                         int(bounds_cap), ctypes.byref(np_out)))
+    k = min(int(np_out.value), int(bounds_cap))
+    return tip_t[:n], part[:n], init[:n], bounds[:k], int(np_out.value)
 
 
 def _batch(ctx: Context, graphs, kind: int, side: int, opts: Opts | None):

@@ -2,8 +2,10 @@
 // marshalling of the caller's graph, phase timing, error translation.
 #include <algorithm>
 #include <chrono>
-#include <string>
+#include <cstdio>
 #include <cstring>
+#include <string>
+#include <vector>
 
 #include "pbng_internal.h"
 
@@ -77,6 +79,46 @@ pbng_opts default_opts(const pbng_opts *o) {
     pbng_opts d{};
     if (o) d = *o;
     return d;
+}
+
+// A NumPy .npy file holding exactly n little-endian float32 values in C
+// order: magic, version, header length, a Python-literal header dict, data.
+// Returns an empty string on success, else what is wrong.
+std::string read_npy_f32(const char *path, i64 n, std::vector<float> &out) {
+    FILE *f = fopen(path, "rb");
+    if (!f) return "cannot open";
+    struct Closer {
+        FILE *f;
+        ~Closer() { fclose(f); }
+    } closer{f};
+    unsigned char pre[10];
+    if (fread(pre, 1, 8, f) != 8 || memcmp(pre, "\x93NUMPY", 6) != 0) return "not a .npy file";
+    const int major = pre[6];
+    size_t hlen = 0;
+    if (major == 1) {
+        if (fread(pre, 1, 2, f) != 2) return "truncated header";
+        hlen = (size_t)pre[0] | ((size_t)pre[1] << 8);
+    } else if (major == 2 || major == 3) {
+        if (fread(pre, 1, 4, f) != 4) return "truncated header";
+        hlen = (size_t)pre[0] | ((size_t)pre[1] << 8) | ((size_t)pre[2] << 16) | ((size_t)pre[3] << 24);
+    } else {
+        return "unknown .npy version";
+    }
+    if (hlen > (1u << 20)) return "header too long";
+    std::string h(hlen, '\0');
+    if (fread(&h[0], 1, hlen, f) != hlen) return "truncated header";
+    auto compact = [](std::string t) {
+        t.erase(std::remove_if(t.begin(), t.end(), [](char ch) { return ch == ' ' || ch == '\n'; }), t.end());
+        return t;
+    };
+    const std::string hc = compact(h);
+    if (hc.find("'descr':'<f4'") == std::string::npos) return "dtype is not little-endian float32";
+    if (hc.find("'fortran_order':False") == std::string::npos) return "not in C order";
+    const std::string shape = "'shape':(" + std::to_string(n) + ",)";
+    if (hc.find(shape) == std::string::npos) return "shape is not (" + std::to_string(n) + ",)";
+    out.resize((size_t)n);
+    if (fread(out.data(), sizeof(float), (size_t)n, f) != (size_t)n) return "truncated data";
+    return "";
 }
 
 double ms_since(std::chrono::steady_clock::time_point t0) {
@@ -214,6 +256,57 @@ int pbng_tip(pbng_ctx *x, const pbng_csr *g, pbng_side side, const pbng_opts *op
         c.stats.ms_prep = ms_since(t0);
         tip_decompose(c, G, side, o, ob.dev);
         ob.finish();
+        if (o.flags & PBNG_F_KERNEL_TIMING) c.timing_end_call();
+        c.stats.ms_total = ms_since(t0);
+    });
+}
+
+int pbng_tip_schedule(pbng_ctx *x, const pbng_csr *g, pbng_side side, const pbng_opts *opts, uint64_t *tip_out,
+                      int32_t *part_out, uint64_t *init_out, uint64_t *bounds_out, int32_t bounds_cap, int32_t *nparts) {
+    if (!x) return PBNG_E_ARG;
+    Ctx &c = x->c;
+    int rc = check_csr(g);
+    if (rc) return fail(c, rc, "bad graph arguments");
+    if (side != PBNG_SIDE_U && side != PBNG_SIDE_V) return fail(c, PBNG_E_ARG, "bad side");
+    const i64 nout = side == PBNG_SIDE_U ? g->n_u : g->n_v;
+    if (nout > 0 && (!tip_out || !part_out || !init_out)) return fail(c, PBNG_E_ARG, "null output");
+    if (bounds_cap < 0 || (bounds_cap > 0 && !bounds_out) || !nparts) return fail(c, PBNG_E_ARG, "bad bounds output");
+    CallScope scope(c);
+    pbng_opts o = default_opts(opts);
+    struct SchedReset {
+        Ctx &c;
+        ~SchedReset() {
+            c.sched_part = nullptr;
+            c.sched_init = nullptr;
+            c.sched_bounds = nullptr;
+            c.sched_cap = 0;
+        }
+    } reset{c};
+    return guarded(c, [&] {
+        auto t0 = std::chrono::steady_clock::now();
+        c.timing_begin_call((o.flags & PBNG_F_KERNEL_TIMING) != 0);
+        const bool host = !g->on_device;
+        pbng_csr dg = device_graph(c, *g);
+        OutBuf ob(c, tip_out, nout, host);
+        c.sched_part = host ? c.alloc<i32>(nout) : part_out;
+        c.sched_init = host ? c.alloc<u64>(nout) : init_out;
+        c.sched_bounds = host ? c.alloc<u64>(bounds_cap) : bounds_out;
+        c.sched_cap = bounds_cap;
+        c.sched_np = 0;
+        DevGraph G;
+        build_graph(c, dg, G);
+        PBNG_HIP(hipStreamSynchronize(c.stream));
+        c.stats.ms_prep = ms_since(t0);
+        if (nout > 0) tip_decompose(c, G, side, o, ob.dev);
+        if (host && nout > 0) {
+            PBNG_HIP(hipMemcpyAsync(part_out, c.sched_part, sizeof(i32) * nout, hipMemcpyDeviceToHost, c.stream));
+            PBNG_HIP(hipMemcpyAsync(init_out, c.sched_init, sizeof(u64) * nout, hipMemcpyDeviceToHost, c.stream));
+            const i32 nb = std::min<i32>(c.sched_np, bounds_cap);
+            if (nb > 0)
+                PBNG_HIP(hipMemcpyAsync(bounds_out, c.sched_bounds, sizeof(u64) * nb, hipMemcpyDeviceToHost, c.stream));
+        }
+        ob.finish();
+        *nparts = c.sched_np;
         if (o.flags & PBNG_F_KERNEL_TIMING) c.timing_end_call();
         c.stats.ms_total = ms_since(t0);
     });
@@ -410,6 +503,16 @@ int pbng_tip_features(pbng_ctx *x, const pbng_csr *g, pbng_side side, float *fea
             PBNG_HIP(hipMemcpyAsync(feat, F, sizeof(float) * nx * 8, hipMemcpyDeviceToHost, c.stream));
         PBNG_HIP(hipStreamSynchronize(c.stream));
     });
+}
+
+int pbng_predictor_load(pbng_ctx *x, const char *path) {
+    if (!x) return PBNG_E_ARG;
+    Ctx &c = x->c;
+    if (!path) return fail(c, PBNG_E_ARG, "null path");
+    std::vector<float> p;
+    const std::string err = read_npy_f32(path, PBNG_MLP_NPARAM, p);
+    if (!err.empty()) return fail(c, PBNG_E_ARG, std::string(path) + ": " + err);
+    return guarded(c, [&] { mlp_set(c, p.data()); });
 }
 
 int pbng_mlp_init(pbng_ctx *x, uint64_t seed) {

@@ -82,6 +82,14 @@ struct Ctx {
     // stream used only to capture round graphs (replayed on `stream`)
     hipStream_t cap_stream = nullptr;
     hipStream_t capture_stream();
+    // schedule outputs of a tip call (device pointers, set by
+    // pbng_tip_schedule for one call): partition of each vertex, support at
+    // its partition's start, exclusive upper bound of each partition
+    i32 *sched_part = nullptr;
+    u64 *sched_init = nullptr;
+    u64 *sched_bounds = nullptr;
+    i32 sched_cap = 0;
+    i32 sched_np = 0;
     // second stream for work that overlaps the context stream's
     hipStream_t aux_stream = nullptr;
     hipStream_t aux();

@@ -49,19 +49,13 @@ struct TipCtl {
     u32 nbin[5];    // active-set bins: small, medium, hash ranges, key tiles, pair intersections
     u32 next[5];    // work counters
     u32 ndirty;     // Y lists to compact
-    u32 nyt;        // pull rounds: Y vertices touched by the active set
-    u32 nrecv;      // pull rounds: receivers
     u32 pad;
-    u64 pw;         // pull rounds: receiver wedges
+    u64 tnext;      // work counter of the key-tile items (vertex x tile)
 };
 
-// Active sets at least this large may be peeled from the receiving side
-// (off by default: on the power-law workloads measured so far the key-tile
-// path is faster; PBNG_PULL_MIN_F turns it on for tuning).
-constexpr u32 PULL_MIN_F = 0xFFFFFFFFu;
-
 // Heavy active vertices accumulate c(x, x') in LDS over key tiles of
-// 2^TILE_LOG consecutive X ids, two 16-bit counters per 32-bit word.
+// 2^TILE_LOG consecutive X ids, two 16-bit counters per 32-bit word, or of
+// 2^(TILE_LOG - 1) ids with 32-bit counters when a degree reaches 2^16.
 constexpr int TILE_LOG = 16;
 // active vertices with more wedges than this take the key-tile path
 constexpr i64 HUGE_W = i64(1) << 16;
@@ -100,6 +94,7 @@ struct PeelArgs {
     u32 *dntouch;
     i32 ntiles;
     i64 nx;
+    u64 *tnext;          // key-tile item counter
     u64 *wedges;
     KCounters *kc;
 };
@@ -287,70 +282,46 @@ __global__ __launch_bounds__(BLOCK) void k_tip_peel_hash(PeelArgs a, int bin) {
     tl.flush(a.kc, a.wedges);
 }
 
-__global__ __launch_bounds__(256) void k_tip_peel_dense(PeelArgs a, int bin) {
-    constexpr int BLOCK = 256;
-    __shared__ i32 s_pre[BLOCK];
-    __shared__ i64 s_moff[BLOCK];
-    __shared__ i32 s_wave[BLOCK / WAVE];
-    __shared__ u64 s_red[BLOCK / WAVE];
-    __shared__ i64 s_bcast[1];
-    __shared__ i32 s_item;
-    ItemSmem sm{s_pre, s_moff, s_wave, s_red, s_bcast};
-    DenseAcc A;
-    A.c = a.dcnt + (i64)blockIdx.x * a.nx;
-    A.bids = nullptr;
-    A.touch = a.dtouch + (i64)blockIdx.x * a.nx;
-    A.ntouch = a.dntouch + blockIdx.x;
-    const u32 n = a.nitems[bin];
-    Tally tl;
-    for (;;) {
-        if (threadIdx.x == 0) s_item = (i32)atomicAdd(&a.next[bin], 1u);
-        __syncthreads();
-        const i32 item = s_item;
-        __syncthreads();
-        if ((u32)item >= n) break;
-        peel_item<BLOCK>(a, a.items[item], A, sm, tl);
-        A.reset(threadIdx.x, BLOCK);
-    }
-    tl.flush(a.kc, a.wedges);
-}
-
 // Heavy active vertices: the live Y lists are sorted by X id, so the wedges
 // of x whose far end lies in a key tile [r0, r0 + 2^TLOG) form one run of
 // every list.  A work item is one (vertex, tile) pair, so the tiles of one
 // vertex run on different workgroups at once: each finds the run of every
-// neighbour's list by binary search, counts the run's wedges in LDS (two
-// 16-bit counters per word; a count never exceeds d_x < 2^16).  A counter
-// word that leaves zero sets its bit in a touched bitmap, and the epilogue
-// visits only the touched words, turning counts c >= 2 into updates.  Key
-// tiles are disjoint, so every (x, x') pair is completed by exactly one item.
-// No global atomic is issued per wedge.
-template <int TLOG>
+// neighbour's list by binary search and counts the run's wedges in LDS.  A
+// count c(x, x') never exceeds the degree of x, so when every degree of the
+// graph is below 2^16 (PACK) two 16-bit counters share a word and a tile
+// covers 2^16 keys; otherwise each key has a 32-bit counter and a tile
+// covers 2^15 keys in the same LDS.  A counter word that leaves zero sets
+// its bit in a touched bitmap, and the epilogue visits only the touched
+// words, turning counts c >= 2 into updates.  Key tiles are disjoint, so
+// every (x, x') pair is completed by exactly one item.  No global atomic is
+// issued per wedge.
+template <int TLOG, bool PACK>
 __global__ __launch_bounds__(512) void k_tip_peel_tiled(PeelArgs a, int bin) {
     constexpr int BLOCK = 512;
-    constexpr int WORDS = (1 << TLOG) / 2;
+    constexpr int KPW = PACK ? 2 : 1;  // keys per counter word
+    constexpr int WORDS = (1 << TLOG) / KPW;
     constexpr int BWORDS = WORDS / 32;
     __shared__ u32 cnt[WORDS];
     __shared__ u32 bm[BWORDS];
     __shared__ i32 s_pre[BLOCK];
     __shared__ i64 s_moff[BLOCK];
     __shared__ i32 s_wave[BLOCK / WAVE];
-    __shared__ u32 s_item;
+    __shared__ u64 s_item;
     for (int i = threadIdx.x; i < WORDS; i += BLOCK) cnt[i] = 0;
     for (int i = threadIdx.x; i < BWORDS; i += BLOCK) bm[i] = 0;
-    const u32 nt = (u32)a.ntiles;
+    const u64 nt = (u64)a.ntiles;
     const u64 n = (u64)a.nitems[bin] * nt;
     const u64 B = *a.bound;
     Tally tl;
     __syncthreads();
     for (;;) {
-        if (threadIdx.x == 0) s_item = atomicAdd(&a.next[bin], 1u);
+        if (threadIdx.x == 0) s_item = atomicAdd((unsigned long long *)a.tnext, 1ull);
         __syncthreads();
-        const u32 item = s_item;
+        const u64 item = s_item;
         __syncthreads();
-        if ((u64)item >= n) break;
+        if (item >= n) break;
         const i32 x = a.items[item / nt];
-        const u32 t = item % nt;
+        const u32 t = (u32)(item % nt);
         const i64 r0 = (i64)t << TLOG;
         const i64 r1 = r0 + (i64(1) << TLOG) < a.nx ? r0 + (i64(1) << TLOG) : a.nx;
         const i64 jb = a.xrow[x];
@@ -405,35 +376,43 @@ __global__ __launch_bounds__(512) void k_tip_peel_tiled(PeelArgs a, int bin) {
                     if (xp == x) continue;
                     ++tl.wedges;
                     const i32 o = xp - (i32)r0;
-                    const u32 wi = (u32)o >> 1;
-                    if (atomicAdd(&cnt[wi], 1u << ((o & 1) << 4)) == 0u) atomicOr(&bm[wi >> 5], 1u << (wi & 31));
+                    const u32 wi = PACK ? (u32)o >> 1 : (u32)o;
+                    const u32 inc = PACK ? 1u << ((o & 1) << 4) : 1u;
+                    if (atomicAdd(&cnt[wi], inc) == 0u) atomicOr(&bm[wi >> 5], 1u << (wi & 31));
                 }
             }
             __syncthreads();
         }
         if (!any) continue;
-        const i32 nbw = (i32)(((r1 - r0 + 1) >> 1) + 31) >> 5;
+        const i32 nbw = (i32)(((r1 - r0 + KPW - 1) / KPW) + 31) >> 5;
         for (i32 bw = threadIdx.x; bw < nbw; bw += BLOCK) {
             u32 bits = bm[bw];
             if (!bits) continue;
             bm[bw] = 0;
             while (bits) {
-                // up to four touched words (eight keys) per batch
+                // up to 8 / KPW touched words (eight keys) per batch
                 i32 kk[8];
                 u32 cc[8];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    kk[2 * q] = kk[2 * q + 1] = -1;
-                    cc[2 * q] = cc[2 * q + 1] = 0;
+                for (int q = 0; q < 8 / KPW; ++q) {
+#pragma unroll
+                    for (int h = 0; h < KPW; ++h) {
+                        kk[KPW * q + h] = -1;
+                        cc[KPW * q + h] = 0;
+                    }
                     if (bits) {
                         const i32 wi = bw * 32 + (__ffs(bits) - 1);
                         bits &= bits - 1;
                         const u32 v = cnt[wi];
                         cnt[wi] = 0;
-                        cc[2 * q] = v & 0xFFFFu;
-                        cc[2 * q + 1] = v >> 16;
-                        kk[2 * q] = (i32)r0 + 2 * wi;
-                        kk[2 * q + 1] = (i32)r0 + 2 * wi + 1;
+                        if (PACK) {
+                            cc[KPW * q] = v & 0xFFFFu;
+                            cc[KPW * q + 1] = v >> 16;
+                        } else {
+                            cc[KPW * q] = v;
+                        }
+#pragma unroll
+                        for (int h = 0; h < KPW; ++h) kk[KPW * q + h] = (i32)r0 + KPW * wi + h;
                     }
                 }
                 apply_updates<8>(a, B, kk, cc, tl);
@@ -702,351 +681,6 @@ __global__ void k_tip_peel_pairs(PeelArgs a, int bin) {
     tl.flush(a.kc, a.wedges);
 }
 
-// Heavy active vertices, streaming form: every wedge issues one
-// fire-and-forget increment of a per-workgroup HBM counter c[x'] and sets
-// bit x' of a touched bitmap held in LDS (one bit per X vertex).  After the
-// vertex's wedges, the bitmap is scanned; each touched counter is read,
-// cleared, and turned into the C(c, 2) update.  Waves never wait on an
-// atomic's return value while streaming wedges.
-template <int NBW>
-__global__ __launch_bounds__(512) void k_tip_peel_bits(PeelArgs a, int bin) {
-    constexpr int BLOCK = 512;
-    __shared__ u32 bm[NBW];
-    __shared__ i32 s_pre[BLOCK];
-    __shared__ i64 s_moff[BLOCK];
-    __shared__ i32 s_wave[BLOCK / WAVE];
-    __shared__ i32 s_item;
-    const i32 nwords = (i32)((a.nx + 31) >> 5);
-    for (i32 i = threadIdx.x; i < nwords; i += BLOCK) bm[i] = 0;
-    u32 *cnt = a.dcnt + (i64)blockIdx.x * a.nx;
-    const u32 n = a.nitems[bin];
-    const u64 B = *a.bound;
-    Tally tl;
-    __syncthreads();
-    for (;;) {
-        if (threadIdx.x == 0) s_item = (i32)atomicAdd(&a.next[bin], 1u);
-        __syncthreads();
-        const i32 item = s_item;
-        __syncthreads();
-        if ((u32)item >= n) break;
-        const i32 x = a.items[item];
-        const i64 jb = a.xrow[x], je = a.xrow[x + 1];
-        if (threadIdx.x == 0) {
-            tl.segments += (u64)(je - jb);
-            tl.items += 1;
-        }
-        for (i64 cb = jb; cb < je; cb += BLOCK) {
-            const i64 j = cb + threadIdx.x;
-            i32 pl = 0;
-            i64 moff = 0;
-            if (j < je) {
-                const i32 y = a.xadj[j];
-                pl = a.ylen[y];
-                moff = a.yrow[y];
-            }
-            i32 tot;
-            const i32 incl = block_incl_scan_i32<BLOCK>(pl, s_wave, tot);
-            if (tot == 0) continue;  // block-uniform
-            s_pre[threadIdx.x] = incl;
-            s_moff[threadIdx.x] = moff;
-            __syncthreads();
-            for (i32 k = threadIdx.x; k < tot; k += BLOCK) {
-                int lo = 0, hi = BLOCK - 1;
-                while (lo < hi) {
-                    int md = (lo + hi) >> 1;
-                    if (s_pre[md] > k) hi = md; else lo = md + 1;
-                }
-                const i32 before = lo ? s_pre[lo - 1] : 0;
-                const i32 xp = a.yadj[s_moff[lo] + (k - before)];
-                if (xp == x) continue;
-                ++tl.wedges;
-                // the counters are private to this workgroup: workgroup scope
-                // keeps the increment in this XCD's L2
-                __hip_atomic_fetch_add(&cnt[xp], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                atomicOr(&bm[xp >> 5], 1u << (xp & 31));
-            }
-            __syncthreads();
-        }
-        // every wave waits for its increments to complete before the scan
-        __threadfence();
-        __syncthreads();
-        for (i32 wi = threadIdx.x; wi < nwords; wi += BLOCK) {
-            u32 v = bm[wi];
-            if (!v) continue;
-            bm[wi] = 0;
-            while (v) {
-                const int b = __ffs(v) - 1;
-                v &= v - 1;
-                const i32 xp = (wi << 5) + b;
-                const u64 cc = __hip_atomic_exchange(&cnt[xp], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                if (cc < 2 || a.st[xp] != ST_ALIVE) continue;
-                const u64 dd = cc * (cc - 1) / 2;
-                atomicAdd((unsigned long long *)&a.sup[xp], (unsigned long long)(0ull - dd));
-                ++tl.atomics;
-            }
-        }
-        __syncthreads();
-    }
-    tl.flush(a.kc, a.wedges);
-}
-
-// ------------------------------------------------------------------ pull rounds
-// For large active sets the same updates are computed from the receiving
-// side.  Every Y vertex touched by the active set gets the list of its
-// active neighbours (by index f into the active set); each alive x' next to
-// a touched y then counts c(x', f) over y in N_x' in LDS and lowers its own
-// support by the sum of C(c, 2): one owner per x', no atomics per wedge, and
-// the active lists are small enough to stay in cache.
-
-struct PullArgs {
-    const i64 *xrow;
-    const i32 *xadj;
-    const i32 *F;        // active set
-    const u32 *nF;
-    const i32 *acnt;     // [ny] active neighbours of y (0 if untouched)
-    const i64 *aoff;     // [ny] start of y's active list in act
-    const i32 *act;      // active lists (indices into F)
-    const u64 *wp;       // [nx] pull wedges of x'
-    const i32 *items;
-    const u32 *nitems;
-    u32 *next;
-    u64 *sup;
-    const u64 *bound;
-    i32 *nf;
-    u32 *nnf;
-    u32 *dcnt;           // HBM counters over active indices, per workgroup
-    i32 *dtouch;
-    u32 *dntouch;
-    i64 dstride;
-    u64 *wedges;
-    KCounters *kc;
-};
-
-// y's touched by the active set: count active neighbours, list the y's
-__global__ void k_act_count(const i32 *F, const u32 *nF, const i64 *xrow, const i32 *xadj, i32 *acnt, i32 *ytouch,
-                            u32 *nytouch) {
-    const int lane = threadIdx.x & (WAVE - 1);
-    const i64 wave = (blockIdx.x * (i64)blockDim.x + threadIdx.x) / WAVE;
-    const i64 nwaves = (i64)gridDim.x * blockDim.x / WAVE;
-    const u32 n = *nF;
-    for (i64 f = wave; f < n; f += nwaves) {
-        const i32 x = F[f];
-        for (i64 j = xrow[x] + lane; j < xrow[x + 1]; j += WAVE) {
-            const i32 y = xadj[j];
-            if (atomicAdd(&acnt[y], 1) == 0) {
-                u32 p = atomicAdd(nytouch, 1u);
-                ytouch[p] = y;
-            }
-        }
-    }
-}
-
-__global__ void k_act_gather(const i32 *ytouch, const u32 *nytouch, const i32 *acnt, i64 *tmp) {
-    const u32 n = *nytouch;
-    for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x)
-        tmp[i] = acnt[ytouch[i]];
-}
-
-__global__ void k_act_offsets(const i32 *ytouch, const u32 *nytouch, const i64 *pre, i64 *aoff, i32 *acur) {
-    const u32 n = *nytouch;
-    for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) {
-        const i32 y = ytouch[i];
-        aoff[y] = pre[i];
-        acur[y] = 0;
-    }
-}
-
-__global__ void k_act_fill(const i32 *F, const u32 *nF, const i64 *xrow, const i32 *xadj, const i64 *aoff, i32 *acur,
-                           i32 *act) {
-    const int lane = threadIdx.x & (WAVE - 1);
-    const i64 wave = (blockIdx.x * (i64)blockDim.x + threadIdx.x) / WAVE;
-    const i64 nwaves = (i64)gridDim.x * blockDim.x / WAVE;
-    const u32 n = *nF;
-    for (i64 f = wave; f < n; f += nwaves) {
-        const i32 x = F[f];
-        for (i64 j = xrow[x] + lane; j < xrow[x + 1]; j += WAVE) {
-            const i32 y = xadj[j];
-            act[aoff[y] + atomicAdd(&acur[y], 1)] = (i32)f;
-        }
-    }
-}
-
-// Receivers: alive x' in the live list of a touched y; wp[x'] accumulates
-// sum over y of |active neighbours of y| (the pull wedges of x').  One wave
-// per touched y.
-__global__ void k_pull_discover(const i32 *ytouch, const u32 *nytouch, const i64 *yrow, const i32 *yadj, const i32 *ylen,
-                                const i32 *acnt, const unsigned char *st, u64 *wp, i32 *rlist, u32 *nr) {
-    const int lane = threadIdx.x & (WAVE - 1);
-    const i64 wave = (blockIdx.x * (i64)blockDim.x + threadIdx.x) / WAVE;
-    const i64 nwaves = (i64)gridDim.x * blockDim.x / WAVE;
-    const u32 n = *nytouch;
-    for (i64 i = wave; i < n; i += nwaves) {
-        const i32 y = ytouch[i];
-        const u32 a = (u32)acnt[y];
-        const i64 b = yrow[y];
-        const i32 len = ylen[y];
-        for (i32 k = lane; k < len; k += WAVE) {
-            const i32 xp = yadj[b + k];
-            if (st[xp] != ST_ALIVE) continue;
-            if (atomicAdd((unsigned long long *)&wp[xp], (unsigned long long)a) == 0) {
-                u32 p = atomicAdd(nr, 1u);
-                rlist[p] = xp;
-            }
-        }
-    }
-}
-
-// bins of receivers: small / medium LDS hash, large (LDS dense or HBM)
-__global__ void k_pull_bin(const i32 *rlist, const u32 *nr, const u64 *wp, i32 *lists, i64 stride, u32 *nbin, u64 *wsum) {
-    const u32 n = *nr;
-    u64 s = 0;
-    for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) {
-        const i32 xp = rlist[i];
-        const u64 w = wp[xp];
-        s += w;
-        if (w < 2) continue;
-        const int b = w <= (u64)T_SMALL_W ? 0 : (w <= (u64)T_MEDIUM_W ? 1 : 2);
-        const u32 p = atomicAdd(&nbin[b], 1u);
-        lists[b * stride + p] = xp;
-    }
-    for (int d = WAVE / 2; d > 0; d >>= 1) s += __shfl_down(s, d, WAVE);
-    if ((threadIdx.x & 63) == 0 && s) atomicAdd((unsigned long long *)wsum, (unsigned long long)s);
-}
-
-__global__ void k_pull_clear(const i32 *ytouch, const u32 *nytouch, i32 *acnt, const i32 *rlist, const u32 *nr, u64 *wp) {
-    const u32 ny = *nytouch, n = *nr;
-    for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < ny; i += (i64)gridDim.x * blockDim.x) acnt[ytouch[i]] = 0;
-    for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) wp[rlist[i]] = 0;
-}
-
-// One receiver x': count c(x', f) over the active lists of its neighbours,
-// then its support loses the sum of C(c, 2).
-template <int BLOCK, class Acc>
-__device__ __forceinline__ void pull_item(const PullArgs &a, i32 xp, Acc &A, const ItemSmem &sm, Tally &t) {
-    const i64 jb = a.xrow[xp], je = a.xrow[xp + 1];
-    if (threadIdx.x == 0) {
-        t.segments += (u64)(je - jb);
-        t.items += 1;
-    }
-    for (i64 cb = jb; cb < je; cb += BLOCK) {
-        const i64 j = cb + threadIdx.x;
-        i32 pl = 0;
-        i64 moff = 0;
-        if (j < je) {
-            const i32 y = a.xadj[j];
-            pl = a.acnt[y];
-            if (pl) moff = a.aoff[y];
-        }
-        i32 tot;
-        const i32 incl = block_incl_scan_i32<BLOCK>(pl, sm.wave, tot);
-        if (tot == 0) continue;  // block-uniform
-        sm.pre[threadIdx.x] = incl;
-        sm.moff[threadIdx.x] = moff;
-        __syncthreads();
-        for (i32 k = threadIdx.x; k < tot; k += BLOCK) {
-            int lo = 0, hi = BLOCK - 1;
-            while (lo < hi) {
-                int md = (lo + hi) >> 1;
-                if (sm.pre[md] > k) hi = md; else lo = md + 1;
-            }
-            const i32 before = lo ? sm.pre[lo - 1] : 0;
-            A.add(a.act[sm.moff[lo] + (k - before)]);
-            ++t.wedges;
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) sm.bcast[0] = A.entries();
-    __syncthreads();
-    const i64 ne = sm.bcast[0];
-    __syncthreads();
-    u64 delta = 0;
-    for (i64 i = threadIdx.x; i < ne; i += BLOCK) {
-        i32 key;
-        u32 c32;
-        A.entry(i, key, c32);
-        if (key < 0 || c32 < 2) continue;
-        const u64 cc = c32;
-        delta += cc * (cc - 1) / 2;
-    }
-    delta = block_sum_u64<BLOCK>(delta, sm.red);
-    if (threadIdx.x == 0 && delta) {
-        const u64 B = *a.bound;
-        const u64 old = a.sup[xp];
-        const u64 nv = old - delta;
-        a.sup[xp] = nv;
-        ++t.atomics;
-        if (old >= B && nv < B) {
-            u32 p = atomicAdd(a.nnf, 1u);
-            a.nf[p] = xp;
-        }
-    }
-    __syncthreads();
-}
-
-template <int BLOCK, int LOGCAP>
-__global__ __launch_bounds__(BLOCK) void k_pull_hash(PullArgs a, int bin) {
-    constexpr int CAP = 1 << LOGCAP;
-    __shared__ i32 s_keys[CAP];
-    __shared__ u32 s_vals[CAP];
-    __shared__ i32 s_pre[BLOCK];
-    __shared__ i64 s_moff[BLOCK];
-    __shared__ i32 s_wave[BLOCK / WAVE];
-    __shared__ u64 s_red[BLOCK / WAVE];
-    __shared__ i64 s_bcast[1];
-    __shared__ i32 s_item;
-    ItemSmem sm{s_pre, s_moff, s_wave, s_red, s_bcast};
-    LdsAcc A;
-    A.keys = s_keys;
-    A.vals = s_vals;
-    A.bids = nullptr;
-    const u32 n = a.nitems[bin];
-    Tally tl;
-    for (;;) {
-        if (threadIdx.x == 0) s_item = (i32)atomicAdd(&a.next[bin], 1u);
-        __syncthreads();
-        const i32 item = s_item;
-        __syncthreads();
-        if ((u32)item >= n) break;
-        const i32 xp = a.items[item];
-        const i64 w = a.wp[xp];
-        int logcap = 6;
-        while ((i64(1) << logcap) < 2 * w && logcap < LOGCAP) ++logcap;
-        A.init(logcap, threadIdx.x, BLOCK);
-        __syncthreads();
-        pull_item<BLOCK>(a, xp, A, sm, tl);
-    }
-    tl.flush(a.kc, a.wedges);
-}
-
-// Large receivers: counters over all active indices, in HBM per workgroup.
-__global__ __launch_bounds__(256) void k_pull_dense(PullArgs a, int bin) {
-    constexpr int BLOCK = 256;
-    __shared__ i32 s_pre[BLOCK];
-    __shared__ i64 s_moff[BLOCK];
-    __shared__ i32 s_wave[BLOCK / WAVE];
-    __shared__ u64 s_red[BLOCK / WAVE];
-    __shared__ i64 s_bcast[1];
-    __shared__ i32 s_item;
-    ItemSmem sm{s_pre, s_moff, s_wave, s_red, s_bcast};
-    DenseAcc A;
-    A.c = a.dcnt + (i64)blockIdx.x * a.dstride;
-    A.bids = nullptr;
-    A.touch = a.dtouch + (i64)blockIdx.x * a.dstride;
-    A.ntouch = a.dntouch + blockIdx.x;
-    const u32 n = a.nitems[bin];
-    Tally tl;
-    for (;;) {
-        if (threadIdx.x == 0) s_item = (i32)atomicAdd(&a.next[bin], 1u);
-        __syncthreads();
-        const i32 item = s_item;
-        __syncthreads();
-        if ((u32)item >= n) break;
-        pull_item<BLOCK>(a, a.items[item], A, sm, tl);
-        A.reset(threadIdx.x, BLOCK);
-    }
-    tl.flush(a.kc, a.wedges);
-}
-
 // ------------------------------------------------------------------ CD helpers
 
 // Wedges of each active vertex over the live lists (one wave per vertex),
@@ -1269,8 +903,10 @@ __global__ void k_set_bound(TipCtl *ctl, int last) {
     ctl->wF = 0;
     ctl->est_final = 0;
     for (int b = 0; b < 5; ++b) ctl->nbin[b] = ctl->next[b] = 0;
-    ctl->nyt = ctl->nrecv = 0;
+    ctl->tnext = 0;
 }
+
+__global__ void k_record_bound(const TipCtl *ctl, u64 *out) { *out = ctl->bound; }
 
 __global__ void k_next_round(TipCtl *ctl) {
     // next active set becomes current; counters of the round are cleared
@@ -1278,12 +914,8 @@ __global__ void k_next_round(TipCtl *ctl) {
     ctl->nF2 = 0;
     ctl->wF = 0;
     for (int b = 0; b < 5; ++b) ctl->nbin[b] = ctl->next[b] = 0;
+    ctl->tnext = 0;
     ctl->ndirty = 0;
-    ctl->nyt = ctl->nrecv = 0;
-}
-
-__global__ void k_clear_bins(TipCtl *ctl) {
-    for (int b = 0; b < 5; ++b) ctl->nbin[b] = ctl->next[b] = 0;
 }
 
 __global__ void k_scale(TipCtl *ctl) {
@@ -1390,6 +1022,7 @@ struct FdArgs {
     i32 *lbatch;
     i32 *lheavy;
     i64 maxni;
+    i32 pack16;          // every degree below 2^16: packed 16-bit LDS counters allowed
     u64 *wedges;
     KCounters *kc;
 };
@@ -1586,7 +1219,8 @@ __global__ __launch_bounds__(FD_BLOCK) void k_tip_fd(FdArgs a) {
             __syncthreads();
             // vertices with many wedges: the whole workgroup, one at a time
             const i32 nh = (i32)s_cnt[2];
-            const bool dense = ni <= DENSE_NI;
+            // packed 16-bit counters hold c(x, x') <= degree of x < 2^16
+            const bool dense = ni <= DENSE_NI && a.pack16;
             if (nh > 0 && dense)
                 for (i32 i = threadIdx.x; i < 2 * NW * HCAP; i += BLOCK) hmem[i] = 0;
             __syncthreads();
@@ -1901,7 +1535,10 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
     PBNG_HIP(hipMemsetAsync(tmp, 0, 2 * sizeof(u64), s));
     hipLaunchKernelGGL(k_min_deg_sum, dim3(grid_1d(nx)), dim3(256), 0, s, xrow, xadj, (const i32 *)ydeg, nx, tmp);
     PBNG_LAUNCH_CHECK();
-    const u64 wedge_cnt_bound = read_scalar<u64>(c, tmp);
+    // Section 5.1: a round recounts when its active set's wedges exceed the
+    // counting bound (a positive recount_w replaces the bound; negative: never)
+    const u64 wedge_cnt_bound = o.recount_w == 0 ? read_scalar<u64>(c, tmp)
+                                                 : (o.recount_w < 0 ? ~0ull : (u64)o.recount_w);
     const u64 wedge_total = reduce_sum_u64(c, w, nx);
     const int P = tip_partitions(o, wedge_total, nx);
     c.stats.P_used = P;
@@ -1922,7 +1559,8 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
     // learned rule: predicted tip numbers from the initial graph
     u64 *that = nullptr;
     double *one_dev = nullptr;
-    c.stats.bound_rule_used = o.bound_rule == PBNG_BOUND_RANDOM ? PBNG_BOUND_RANDOM : PBNG_BOUND_PLAIN;
+    c.stats.bound_rule_used = (o.bound_rule == PBNG_BOUND_RANDOM || o.bound_rule == PBNG_BOUND_PAPER) ? o.bound_rule
+                                                                                                 : PBNG_BOUND_PLAIN;
     if (o.bound_rule == PBNG_BOUND_LEARNED && c.mlp_ready) {
         that = c.alloc<u64>(nx);
         learned_theta_hat(c, G, side, sup, that);
@@ -1931,55 +1569,20 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
         PBNG_HIP(hipMemcpyAsync(one_dev, &one, sizeof(double), hipMemcpyHostToDevice, s));
         c.stats.bound_rule_used = PBNG_BOUND_LEARNED;
     }
-    // LDS key tiles for heavy active vertices (one 512-lane workgroup per CU)
-    const i32 ntiles = (i32)((nx + (i64(1) << TILE_LOG) - 1) >> TILE_LOG);
+    // LDS key tiles for heavy active vertices (one 512-lane workgroup per
+    // CU): 2^16 keys with packed 16-bit counters while every degree is below
+    // 2^16 (a count c(x, x') never exceeds the degree of x), else 2^15 keys
+    // with 32-bit counters
+    const bool pack16 = G.maxdeg < 65536;
+    const int tile_log = pack16 ? TILE_LOG : TILE_LOG - 1;
+    const i32 ntiles = (i32)((nx + (i64(1) << tile_log) - 1) >> tile_log);
     const int tslots = c.num_cu;
-    // Active vertices above HUGE_W wedges use LDS key tiles (one work item per
-    // vertex and 2^16-key tile); streaming into HBM counters with an LDS
-    // touched bitmap is the alternative (PBNG_HEAVY=b) while one bit per X
-    // vertex fits in LDS.  Item indices (vertices x tiles) must fit 32 bits.
-    constexpr int BITS_NBW = 1 << 15;
-    const char *heavy_env = getenv("PBNG_HEAVY");
-    const bool huge_bits = heavy_env && heavy_env[0] == 'b' && nx <= (i64)BITS_NBW * 32;
-    const bool huge_tiled = !huge_bits && (u64)nx * (u64)ntiles < (u64(1) << 32);
-    // default threshold: at least 4096 wedges per key tile on average
+    // active vertices above huge_w wedges take the key tiles; default: at
+    // least 4096 wedges per key tile on average
     const u64 huge_w = o.tile_w == 0 ? std::max<u64>((u64)HUGE_W, (u64)ntiles * 4096u)
                                      : (o.tile_w < 0 ? ~0ull : (u64)o.tile_w);
     u32 *hoff = c.alloc<u32>(nx + 1);
     u32 *htotal = c.alloc<u32>(1);
-    const char *pull_env = getenv("PBNG_PULL_MIN_F");
-    const u32 pull_min_f = pull_env ? (u32)atol(pull_env) : PULL_MIN_F;
-    // pull rounds: active lists of touched Y vertices, receivers
-    i32 *acnt = c.alloc<i32>(ny);
-    i64 *aoff = c.alloc<i64>(ny);
-    i32 *acur = c.alloc<i32>(ny);
-    i32 *ytouch = c.alloc<i32>(ny);
-    i32 *act = c.alloc<i32>(m);
-    u64 *wp = c.alloc<u64>(nx);
-    i32 *rlist = c.alloc<i32>(nx);
-    i64 *atmp = c.alloc<i64>(ny + 1);
-    i64 *apre = c.alloc<i64>(ny + 1);
-    PBNG_HIP(hipMemsetAsync(acnt, 0, sizeof(i32) * (ny ? ny : 1), s));
-    PBNG_HIP(hipMemsetAsync(wp, 0, sizeof(u64) * nx, s));
-    PullArgs qa{};
-    qa.xrow = xrow;
-    qa.xadj = xadj;
-    qa.nF = &ctl->nF;
-    qa.acnt = acnt;
-    qa.aoff = aoff;
-    qa.act = act;
-    qa.wp = wp;
-    qa.nitems = ctl->nbin;
-    qa.next = ctl->next;
-    qa.sup = sup;
-    qa.bound = &ctl->bound;
-    qa.nnf = &ctl->nF2;
-    qa.dcnt = dcnt;
-    qa.dtouch = dtouch;
-    qa.dntouch = dntouch;
-    qa.dstride = nx;
-    qa.wedges = &ctl->wedges;
-    qa.kc = c.kctr + PBNG_K_TIP_PEEL;
 
     PeelArgs pa{};
     pa.xrow = xrow;
@@ -1999,6 +1602,7 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
     pa.dntouch = dntouch;
     pa.ntiles = ntiles;
     pa.nx = nx;
+    pa.tnext = &ctl->tnext;
     pa.wedges = &ctl->wedges;
     pa.kc = c.kctr + PBNG_K_TIP_PEEL;
 
@@ -2028,16 +1632,18 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
     // phase (the partition count may then exceed P).
     u64 *plev = c.alloc<u64>((i64)P + nx + 1);
     fill<u64>(c, plev, ~0ull, (i64)P + nx + 1);
+    // exclusive upper bound theta(i+1) of every partition (schedule output)
+    u64 *pbound = c.sched_part ? c.alloc<u64>((i64)P + nx + 1) : nullptr;
     u64 *alive_work = c.alloc<u64>(1);
     bool level_mode = false;
-    // the three thresholds can be overridden from the environment (tests use
-    // this to force single-level partitions on small graphs)
-    const char *lv_alive_env = getenv("PBNG_LEVEL_MAX_ALIVE");
-    const char *lv_work_env = getenv("PBNG_LEVEL_MIN_WORK");
-    const i64 level_max_alive = lv_alive_env ? (i64)atoll(lv_alive_env) : LEVEL_MAX_ALIVE;
-    const u64 level_min_work = lv_work_env ? (u64)strtoull(lv_work_env, nullptr, 10) : LEVEL_MIN_WORK;
-    const char *lv_avg_env = getenv("PBNG_LEVEL_MIN_AVG");
-    const u64 level_min_avg = lv_avg_env ? (u64)strtoull(lv_avg_env, nullptr, 10) : LEVEL_MIN_AVG;
+    // opts.level_alive: 0 = the defaults above; positive = single levels as
+    // soon as at most that many vertices are alive, whatever their work;
+    // negative = never.  The paper's rule (PBNG_BOUND_PAPER) has no levels.
+    const bool paper_rule = o.bound_rule == PBNG_BOUND_PAPER;
+    const i64 level_max_alive =
+        paper_rule || o.level_alive < 0 ? -1 : (o.level_alive > 0 ? (i64)o.level_alive : LEVEL_MAX_ALIVE);
+    const u64 level_min_work = o.level_alive > 0 ? 0 : LEVEL_MIN_WORK;
+    const u64 level_min_avg = o.level_alive > 0 ? 0 : LEVEL_MIN_AVG;
     while (n_alive > 0) {
         const bool at_last = (P - pid) <= 1;
         // work estimate of every alive vertex with the current live degrees
@@ -2092,13 +1698,14 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
                 // so its cost grows with (vertices x levels), which the work
                 // estimate does not see; the target keeps such partitions
                 // near the size whose state fits in LDS
-                const u64 cnt_target =
-                    std::max<u64>((u64)FD_LDS_NI, (u64)(2 * n_alive / std::max<i64>(P - pid, 1)));
+                const u64 cnt_target = paper_rule ? 0
+                    : std::max<u64>((u64)FD_LDS_NI, (u64)(2 * n_alive / std::max<i64>(P - pid, 1)));
                 weighted_select(c, sup, w, st, ST_ALIVE, nx, nullptr, &ctl->scale, P - pid, &ctl->s, &ctl->est_init,
                                 cnt_target);
             }
         }
         hipLaunchKernelGGL(k_set_bound, dim3(1), dim3(1), 0, s, ctl, last ? 1 : 0);
+        if (pbound) hipLaunchKernelGGL(k_record_bound, dim3(1), dim3(1), 0, s, (const TipCtl *)ctl, pbound + pid);
         hipLaunchKernelGGL(k_frontier, dim3(gx), dim3(256), 0, s, st, (const u64 *)sup, (const u64 *)w, init, wsnap, part,
                            nx, ctl, pid, 1, F);
         PBNG_LAUNCH_CHECK();
@@ -2143,45 +1750,6 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
                                    part, nx, ctl, pid, 0, F);
                 PBNG_LAUNCH_CHECK();
                 item_work(F);
-            } else if (nF >= pull_min_f) {
-                // receiving-side round: active lists of the touched Y vertices
-                const int gfw = grid_1d((i64)nF * WAVE);
-                c.kbegin(PBNG_K_TIP_PEEL);
-                hipLaunchKernelGGL(k_act_count, dim3(gfw), dim3(256), 0, s, (const i32 *)F, (const u32 *)&ctl->nF, xrow, xadj,
-                                   acnt, ytouch, &ctl->nyt);
-                PBNG_LAUNCH_CHECK();
-                const u32 nyt = read_scalar<u32>(c, &ctl->nyt);
-                const int gy = grid_1d(std::max<i64>(nyt, 1));
-                hipLaunchKernelGGL(k_act_gather, dim3(gy), dim3(256), 0, s, (const i32 *)ytouch, (const u32 *)&ctl->nyt,
-                                   (const i32 *)acnt, atmp);
-                PBNG_LAUNCH_CHECK();
-                exclusive_scan<i64>(c, atmp, apre, nyt);
-                hipLaunchKernelGGL(k_act_offsets, dim3(gy), dim3(256), 0, s, (const i32 *)ytouch, (const u32 *)&ctl->nyt,
-                                   (const i64 *)apre, aoff, acur);
-                hipLaunchKernelGGL(k_act_fill, dim3(gfw), dim3(256), 0, s, (const i32 *)F, (const u32 *)&ctl->nF, xrow, xadj,
-                                   (const i64 *)aoff, acur, act);
-                hipLaunchKernelGGL(k_pull_discover, dim3(grid_1d((i64)std::max<u32>(nyt, 1) * WAVE)), dim3(256), 0, s,
-                                   (const i32 *)ytouch, (const u32 *)&ctl->nyt, yrow, (const i32 *)yadj, (const i32 *)ylen,
-                                   (const i32 *)acnt, (const unsigned char *)st, wp, rlist, &ctl->nrecv);
-                hipLaunchKernelGGL(k_clear_bins, dim3(1), dim3(1), 0, s, ctl);
-                hipLaunchKernelGGL(k_pull_bin, dim3(grid_1d(nx)), dim3(256), 0, s, (const i32 *)rlist, (const u32 *)&ctl->nrecv,
-                                   (const u64 *)wp, bins, nx, ctl->nbin, &ctl->pw);
-                PBNG_LAUNCH_CHECK();
-                qa.F = F;
-                qa.nf = F2;
-                PullArgs q2 = qa;
-                q2.items = bins + 2 * nx;
-                PullArgs q1 = qa;
-                q1.items = bins + nx;
-                PullArgs q0 = qa;
-                q0.items = bins;
-                hipLaunchKernelGGL(k_pull_dense, dim3(slots), dim3(256), 0, s, q2, 2);
-                hipLaunchKernelGGL((k_pull_hash<256, 13>), dim3((i64)c.num_cu * 2), dim3(256), 0, s, q1, 1);
-                hipLaunchKernelGGL((k_pull_hash<64, 10>), dim3((i64)c.num_cu * 16), dim3(64), 0, s, q0, 0);
-                hipLaunchKernelGGL(k_pull_clear, dim3(grid_1d(nx)), dim3(256), 0, s, (const i32 *)ytouch,
-                                   (const u32 *)&ctl->nyt, acnt, (const i32 *)rlist, (const u32 *)&ctl->nrecv, wp);
-                c.kend(PBNG_K_TIP_PEEL);
-                PBNG_LAUNCH_CHECK();
             } else {
                 pa.items = bins;
                 pa.nf = F2;
@@ -2192,19 +1760,19 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
                 PeelArgs pm = pa;
                 pm.items = bins + nx;
                 c.kbegin(PBNG_K_TIP_PEEL);
-                if (huge_tiled) {
+                {
                     c.kend(PBNG_K_TIP_PEEL);
                     PeelArgs pk = pd;
                     pk.kc = c.kctr + PBNG_K_TIP_TILED;
                     c.kbegin(PBNG_K_TIP_TILED);
-                    hipLaunchKernelGGL(k_tip_peel_tiled<TILE_LOG>, dim3(std::min<i64>(tslots, (i64)nF * ntiles)), dim3(512), 0, s,
-                                       pk, 3);
+                    const dim3 tg((unsigned)std::min<i64>(tslots, (i64)nF * ntiles));
+                    if (pack16)
+                        hipLaunchKernelGGL((k_tip_peel_tiled<TILE_LOG, true>), tg, dim3(512), 0, s, pk, 3);
+                    else
+                        hipLaunchKernelGGL((k_tip_peel_tiled<TILE_LOG - 1, false>), tg, dim3(512), 0, s, pk, 3);
                     c.kend(PBNG_K_TIP_TILED);
                     c.kbegin(PBNG_K_TIP_PEEL);
-                } else if (huge_bits)
-                    hipLaunchKernelGGL(k_tip_peel_bits<BITS_NBW>, dim3(std::min<i64>(slots, nF)), dim3(512), 0, s, pd, 3);
-                else
-                    hipLaunchKernelGGL(k_tip_peel_dense, dim3(std::min<i64>(slots, nF)), dim3(256), 0, s, pd, 3);
+                }
                 hipLaunchKernelGGL(k_range_split, dim3(1), dim3(1024), 0, s, (const i32 *)pt.items, (const u32 *)ctl->nbin, 2,
                                    (const u64 *)wi, hoff, htotal);
                 c.kend(PBNG_K_TIP_PEEL);
@@ -2275,6 +1843,13 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
     c.stats.rho = rho;
     c.stats.recounts = recounts;
     c.stats.partitions = np;
+    if (c.sched_part) {
+        PBNG_HIP(hipMemcpyAsync(c.sched_part, part, sizeof(i32) * nx, hipMemcpyDeviceToDevice, s));
+        PBNG_HIP(hipMemcpyAsync(c.sched_init, init, sizeof(u64) * nx, hipMemcpyDeviceToDevice, s));
+        const i32 nb = std::min<i32>(np, c.sched_cap);
+        if (nb > 0) PBNG_HIP(hipMemcpyAsync(c.sched_bounds, pbound, sizeof(u64) * nb, hipMemcpyDeviceToDevice, s));
+        c.sched_np = np;
+    }
     double t2 = now_ms();
     c.stats.ms_cd = t2 - t1;
 
@@ -2354,6 +1929,7 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
     fa.plev = plev;
     fa.theta = theta;
     fa.maxni = maxni;
+    fa.pack16 = pack16 ? 1 : 0;
     fa.lsup = c.alloc<u64>((i64)fdblocks * maxni);
     fa.lst = c.alloc<unsigned char>((i64)fdblocks * maxni);
     fa.lcnt = c.alloc<u32>((i64)fdblocks * maxni);

@@ -75,54 +75,127 @@ def test_tip_power_law_partitions(ctx, cl_mid, P):
     assert np.array_equal(gpu_tip(ctx, g, 1, P=P), ev)
 
 
-@pytest.fixture
-def force_levels(monkeypatch):
-    """Single-level partitions as soon as at most `max_alive` vertices are
-    left, whatever their work (the default needs a small, heavy core)."""
-    def setup(max_alive=1 << 40):
-        monkeypatch.setenv("PBNG_LEVEL_MAX_ALIVE", str(max_alive))
-        monkeypatch.setenv("PBNG_LEVEL_MIN_WORK", "0")
-        monkeypatch.setenv("PBNG_LEVEL_MIN_AVG", "0")
-    return setup
+ALL_ALIVE = (1 << 31) - 1  # level_alive: single levels from the start
 
 
-@pytest.mark.parametrize("P,max_alive", [(1, 1 << 40), (40, 5000), (150, 800)])
-def test_tip_single_level_partitions(ctx, cl_mid, force_levels, P, max_alive):
+@pytest.mark.parametrize("P,max_alive", [(1, ALL_ALIVE), (40, 5000), (150, 800)])
+def test_tip_single_level_partitions(ctx, cl_mid, P, max_alive):
     """A range holding one support value k gives every vertex tip number k
-    with no fine-grained peeling; ranges first, then single levels once few
-    vertices are left (from the start with P = 1), must reproduce the
-    oracle."""
-    force_levels(max_alive)
+    with no fine-grained peeling; ranges first, then single levels once at
+    most `max_alive` vertices are left whatever their work (from the start
+    with P = 1), must reproduce the oracle."""
     g, eu, ev = cl_mid
-    assert np.array_equal(gpu_tip(ctx, g, 0, P=P), eu)
+    assert np.array_equal(gpu_tip(ctx, g, 0, P=P, level_alive=max_alive), eu)
     if P == 1:
         # every partition is one level: one partition per distinct tip number
         assert ctx.stats()["partitions"] == len(np.unique(eu))
-    assert np.array_equal(gpu_tip(ctx, g, 1, P=P), ev)
+    assert np.array_equal(gpu_tip(ctx, g, 1, P=P, level_alive=max_alive), ev)
 
 
-def test_tip_single_level_small_graphs(ctx, force_levels):
-    force_levels()
+def test_tip_single_level_small_graphs(ctx):
     for s in range(20):
         rng = np.random.default_rng(300 + s)
         g = synth.random_small(int(rng.integers(1, 14)), int(rng.integers(1, 10)), float(rng.choice([0.4, 0.8])), seed=s)
         for side in (0, 1):
             for P in (1, 2):
-                assert np.array_equal(gpu_tip(ctx, g, side, P=P), oracle.tip(g, side)), (g.name, side, P)
+                res = gpu_tip(ctx, g, side, P=P, level_alive=ALL_ALIVE)
+                assert np.array_equal(res, oracle.tip(g, side)), (g.name, side, P)
     for a, b in ((3, 5), (12, 9)):
         g = synth.complete(a, b)
-        assert np.array_equal(gpu_tip(ctx, g, 0, P=1), oracle.tip(g, 0))
+        assert np.array_equal(gpu_tip(ctx, g, 0, P=1, level_alive=ALL_ALIVE), oracle.tip(g, 0))
 
 
-@pytest.mark.parametrize("min_f", [0, 200])
-def test_tip_receiving_side_rounds(ctx, cl_mid, monkeypatch, min_f):
-    """Rounds peeled from the receiving side (off by default; on for every
-    round at min_f = 0, for active sets of 200 or more at min_f = 200) give
-    the oracle's numbers."""
-    monkeypatch.setenv("PBNG_PULL_MIN_F", str(min_f))
+@pytest.mark.parametrize("b,t", [(65535, 65000), (70000, 66000)])
+@pytest.mark.parametrize("P", [1, 2, 0])
+def test_tip_degree_at_least_2_16(ctx, b, t, P):
+    """K_{2,b} plus a vertex x on t of the b columns: x is peeled alone with
+    c(x, u) = t common neighbours, and every tip number is 2 C(t, 2) (the
+    clamp closed form a C(t, 2) >= (a - 1) C(b, 2) with a = 2).  At
+    b = 65535 every count fits 16 bits (the largest packed counter value);
+    at b = 70000 the degrees and counts pass 2^16, which the key-tile and
+    fine-grained counters must hold without carrying or wrapping."""
+    edges = [(u, v) for u in range(2) for v in range(b)] + [(2, v) for v in range(t)]
+    g = synth.from_edges(3, b, edges)
+    exp = 2 * C2(t)
+    assert exp > C2(b)
+    res = gpu_tip(ctx, g, 0, P=P)
+    assert res.tolist() == [exp, exp, exp]
+    assert np.array_equal(res, oracle.tip(g, 0))
+    assert np.array_equal(gpu_tip(ctx, g, 1, P=P), oracle.tip(g, 1))
+
+
+@pytest.mark.parametrize("P", [2, 7, 40])
+def test_tip_recount_rounds(ctx, cl_mid, P):
+    """Section 5.1: a round whose active set has more live wedges than the
+    recount bound recounts the remaining graph instead of peeling.  With the
+    bound forced down to 1 every such round recounts (P = 1 has no rounds:
+    its one partition takes every vertex at once); results are the
+    oracle's."""
     g, eu, ev = cl_mid
-    assert np.array_equal(gpu_tip(ctx, g, 0, P=40), eu)
-    assert np.array_equal(gpu_tip(ctx, g, 1, P=40), ev)
+    assert np.array_equal(gpu_tip(ctx, g, 0, P=P, recount_w=1), eu)
+    assert ctx.stats()["recounts"] > 0
+    assert np.array_equal(gpu_tip(ctx, g, 1, P=P, recount_w=1), ev)
+    assert ctx.stats()["recounts"] > 0
+    for s in range(10):
+        gs = synth.random_small(12, 9, 0.6, seed=700 + s)
+        assert np.array_equal(gpu_tip(ctx, gs, 0, P=3, recount_w=1), oracle.tip(gs, 0))
+
+
+def test_tip_paper_rule(ctx, cl_mid):
+    """The paper's bound rule alone (no vertex-count target, no single
+    levels) gives the same numbers."""
+    g, eu, ev = cl_mid
+    for P in (7, 150):
+        assert np.array_equal(gpu_tip(ctx, g, 0, P=P, bound_rule=pb.BOUND_PAPER), eu)
+        assert ctx.stats()["bound_rule_used"] == pb.BOUND_PAPER
+        assert np.array_equal(gpu_tip(ctx, g, 1, P=P, bound_rule=pb.BOUND_PAPER), ev)
+
+
+def _check_schedule(ctx, g, side, exp, **kw):
+    """Theorem 1 and the initialisation vector: every vertex of partition i
+    has theta(i) <= tip < theta(i+1); bounds increase; a vertex's support at
+    its partition's start equals its butterflies among the vertices of its
+    own and later partitions (the oracle's count on that subgraph)."""
+    dg = pb.DeviceGraph.from_graph(g)
+    th, part, init, bounds, npart = pb.tip_schedule(ctx, dg, side, pb.make_opts(**kw))
+    th, init, bounds = u64(th), u64(init), u64(bounds)
+    part = part.cpu().numpy()
+    assert np.array_equal(th, exp)
+    assert npart == bounds.size and npart >= 1
+    assert (part >= 0).all() and (part < npart).all()
+    assert (np.diff(bounds.astype(object)) > 0).all()
+    lo = np.concatenate([[0], bounds[:-1]]).astype(np.uint64)
+    assert (lo[part] <= th).all() and (th < bounds[part]).all()
+    # initialisation vector against the oracle, partition by partition
+    gx = g if side == 0 else synth.from_edges(g.n_v, g.n_u, list(zip(*reversed(g.edges()))))
+    u, v = gx.edges()
+    for i in np.unique(part):
+        keep = part[u] >= i
+        sub = synth.from_edges(gx.n_u, gx.n_v, list(zip(u[keep], v[keep])))
+        sup = oracle.count_vertex(sub)[0]
+        sel = part == i
+        assert np.array_equal(init[sel], sup[sel]), (side, int(i))
+    return npart
+
+
+@pytest.mark.parametrize("rule", [pb.BOUND_PLAIN, pb.BOUND_PAPER, pb.BOUND_RANDOM])
+def test_tip_schedule_theorem1(ctx, rule):
+    g = synth.config_graph("er_2k_1k_20k")
+    for side in (0, 1):
+        exp = oracle.tip(g, side)
+        npart = _check_schedule(ctx, g, side, exp, P=8, bound_rule=rule, seed=3)
+        # (a random bound may take every vertex into its first partition)
+        assert npart > 1 or rule == pb.BOUND_RANDOM
+    gm = synth.chung_lu(6000, 1500, 40000, 2.1, 800, seed=9)
+    for side in (0, 1):
+        _check_schedule(ctx, gm, side, oracle.tip(gm, side), P=12, bound_rule=rule, seed=5)
+
+
+def test_tip_schedule_levels_and_recounts(ctx):
+    gm = synth.chung_lu(6000, 1500, 40000, 2.1, 800, seed=9)
+    exp = oracle.tip(gm, 0)
+    _check_schedule(ctx, gm, 0, exp, P=6, level_alive=400)
+    _check_schedule(ctx, gm, 0, exp, P=6, recount_w=1)
 
 
 @pytest.mark.parametrize("flags", [pb.F_NO_DYNAMIC, pb.F_NO_BATCH, pb.F_NO_DYNAMIC | pb.F_NO_BATCH])

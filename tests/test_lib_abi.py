@@ -3,6 +3,8 @@ declared in include/pbng.h, and the Python binding mirrors the ABI structs."""
 import ctypes
 import os
 import re
+import subprocess
+import tempfile
 
 import paper_2110_12511_amd as pb
 from paper_2110_12511_amd import binding
@@ -23,11 +25,32 @@ def test_exports_every_declared_symbol():
         assert hasattr(lib, name), name
 
 
+def _c_layout(struct, fields):
+    """sizeof and field offsets of a struct of include/pbng.h as the C
+    compiler lays it out (gcc on the host)."""
+    src = ["#include <stdio.h>", "#include <stddef.h>", '#include "pbng.h"', "int main(void) {",
+           f'  printf("%zu\\n", sizeof({struct}));']
+    src += [f'  printf("%zu\\n", offsetof({struct}, {f}));' for f in fields]
+    src += ["  return 0;", "}"]
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "layout.c")
+        exe = os.path.join(d, "layout")
+        with open(c, "w") as fh:
+            fh.write("\n".join(src) + "\n")
+        subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), c, "-o", exe])
+        vals = [int(v) for v in subprocess.check_output([exe]).split()]
+    return vals[0], vals[1:]
+
+
 def test_struct_layouts():
-    # pbng_csr: 3 x int64 + 2 pointers + int32 (+pad); pbng_opts: 8 x int32
-    assert ctypes.sizeof(binding.Csr) == 48
-    assert ctypes.sizeof(binding.Opts) == 32
-    assert ctypes.sizeof(binding.Stats) == 6 * 8 + 10 * 8 + 4 * 4 + 3 * 8 + binding.K_NCLASS * 32
+    """The ctypes mirrors of pbng_csr, pbng_opts and pbng_stats have the C
+    compiler's size and field offsets."""
+    for struct, cls in (("pbng_csr", binding.Csr), ("pbng_opts", binding.Opts), ("pbng_stats", binding.Stats),
+                        ("pbng_kernel_stat", binding.KernelStat)):
+        fields = [f for f, _ in cls._fields_]
+        size, offs = _c_layout(struct, fields)
+        assert ctypes.sizeof(cls) == size, struct
+        assert [getattr(cls, f).offset for f in fields] == offs, struct
 
 
 def test_null_context_rejected():
