@@ -192,6 +192,21 @@ int pbng_last_stats(pbng_ctx *ctx, pbng_stats *out);
 int pbng_count(pbng_ctx *ctx, const pbng_csr *g, pbng_count_kind kind,
                const pbng_opts *opts, uint64_t *out);
 
+/* pbng_count without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same results as pbng_count.  The graph (on_device
+ * must be 1) and out are the caller's device buffers; every other byte the
+ * call needs comes from one static 64 MiB array per device that the library
+ * holds until the process ends.  Graphs whose relabelled vertex and edge
+ * arrays alone exceed it (40 bytes per edge plus 32 per vertex) return
+ * PBNG_E_OVERFLOW before any work; a graph that passes that check but needs
+ * more scratch (dense counters of large starts, hub tiles) returns
+ * PBNG_E_NOMEM.  Calls on one device share the array and keep the last
+ * call's contents: calls that overlap on one device (two contexts, two host
+ * threads, two streams) race and must be serialised by the caller.        */
+int pbng_count_noalloc(pbng_ctx *ctx, const pbng_csr *g, pbng_count_kind kind,
+                       const pbng_opts *opts, uint64_t *out);
+
 /* Tip numbers of one side (Definition 2; Section 3.2).  tip_out: uint64
  * [n_u] for PBNG_SIDE_U, [n_v] for PBNG_SIDE_V.  opts may be NULL.       */
 int pbng_tip(pbng_ctx *ctx, const pbng_csr *g, pbng_side side,

@@ -118,7 +118,7 @@ class Stats(ctypes.Structure):
 EXPORTS = ["pbng_create", "pbng_destroy", "pbng_last_error", "pbng_last_stats", "pbng_count", "pbng_tip", "pbng_wing",
            "pbng_tip_features", "pbng_mlp_init", "pbng_mlp_set", "pbng_mlp_get", "pbng_mlp_forward",
            "pbng_mlp_loss_grad", "pbng_mlp_train", "pbng_tip_batch", "pbng_wing_batch", "pbng_autotune",
-           "pbng_tip_schedule", "pbng_predictor_load"]
+           "pbng_tip_schedule", "pbng_predictor_load", "pbng_count_noalloc"]
 MLP_NPARAM = 8961
 
 _lib = None
@@ -148,6 +148,8 @@ def load():
     lib.pbng_last_stats.restype = ctypes.c_int
     lib.pbng_count.argtypes = [vp, ctypes.POINTER(Csr), ctypes.c_int, ctypes.POINTER(Opts), vp]
     lib.pbng_count.restype = ctypes.c_int
+    lib.pbng_count_noalloc.argtypes = [vp, ctypes.POINTER(Csr), ctypes.c_int, ctypes.POINTER(Opts), vp]
+    lib.pbng_count_noalloc.restype = ctypes.c_int
     lib.pbng_tip.argtypes = [vp, ctypes.POINTER(Csr), ctypes.c_int, ctypes.POINTER(Opts), vp]
     lib.pbng_tip.restype = ctypes.c_int
     lib.pbng_wing.argtypes = [vp, ctypes.POINTER(Csr), ctypes.POINTER(Opts), vp]

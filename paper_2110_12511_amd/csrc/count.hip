@@ -691,7 +691,12 @@ static void launch_all(Ctx &c, const DevGraph &G, CountArgs a, const Bins &b) {
     u32 *next = c.alloc<u32>(4);
     PBNG_HIP(hipMemsetAsync(next, 0, 4 * sizeof(u32), c.stream));
     a.kc = c.kctr + PBNG_K_COUNT;
-    const int slots = (int)std::min<i64>(b.cnt[3], (i64)c.num_cu);
+    int slots = (int)std::min<i64>(b.cnt[3], (i64)c.num_cu);
+    if (b.cnt[3] && c.arena.fixed_base) {
+        // fixed scratch: as many HBM counter slices as half the room left holds
+        const size_t per = (size_t)std::max<i64>(G.n, 1) * ((MODE & M_BE_FILL) ? 12 : 8);
+        slots = (int)std::max<size_t>(1, std::min<size_t>((size_t)slots, c.arena.fixed_left() / 2 / per));
+    }
     if (b.cnt[3]) {
         a.dcnt = c.alloc<u32>((i64)slots * G.n);
         a.dtouch = c.alloc<i32>((i64)slots * G.n);

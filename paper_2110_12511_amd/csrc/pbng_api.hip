@@ -4,6 +4,7 @@
 #include <chrono>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -13,9 +14,36 @@ struct pbng_ctx {
     pbng::Ctx c;
 };
 
+// Work memory of pbng_count_noalloc: one array per device, held until the
+// process ends.  Host code never uses its name as an address: pbng_create
+// resolves the array's device address on the current device (once per
+// device) and keeps it per device.
+#define PBNG_SCRATCH_BYTES (size_t(64) << 20)
+static __device__ __align__(256) unsigned char scratch[PBNG_SCRATCH_BYTES];
+
 namespace pbng {
 
 namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES];
+
+// Device address of `scratch` on device dev (which must be current): looked
+// up on the first call per device and kept.
+hipError_t scratch_address(int dev, void **out) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
 
 struct CallScope {
     // Returns the arena to its free list when a call ends, however it ends.
@@ -165,6 +193,11 @@ int pbng_create(pbng_ctx **out, void *stream) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, x->c.device) == hipSuccess && prop.multiProcessorCount > 0)
         x->c.num_cu = prop.multiProcessorCount;
+    if (scratch_address(x->c.device, &x->c.scratch) != hipSuccess) {
+        (void)hipGetLastError();
+        delete x;
+        return PBNG_E_DEVICE;
+    }
     // per-class work counters: every traversal kernel adds to them, so they
     // exist for the context's whole life
     if (hipMalloc(&x->c.kctr, sizeof(KCounters) * PBNG_K_NCLASS) != hipSuccess ||
@@ -231,6 +264,63 @@ int pbng_count(pbng_ctx *x, const pbng_csr *g, pbng_count_kind kind, const pbng_
         ob.finish();
         c.stats.ms_count = ms_since(t1);
         if (o.flags & PBNG_F_KERNEL_TIMING) c.timing_end_call();
+        c.stats.ms_total = ms_since(t0);
+    });
+}
+
+int pbng_count_noalloc(pbng_ctx *x, const pbng_csr *g, pbng_count_kind kind, const pbng_opts *opts, uint64_t *out) {
+    if (!x) return PBNG_E_ARG;
+    Ctx &c = x->c;
+    int rc = check_csr(g);
+    if (rc) return fail(c, rc, "bad graph arguments");
+    if (!g->on_device) return fail(c, PBNG_E_ARG, "pbng_count_noalloc needs the graph and output in device memory");
+    if (kind != PBNG_COUNT_VERTEX_U && kind != PBNG_COUNT_VERTEX_V && kind != PBNG_COUNT_EDGE)
+        return fail(c, PBNG_E_ARG, "bad count kind");
+    const i64 nout = kind == PBNG_COUNT_VERTEX_U ? g->n_u : (kind == PBNG_COUNT_VERTEX_V ? g->n_v : g->m);
+    if (nout > 0 && !out) return fail(c, PBNG_E_ARG, "null output");
+    // the vertex and edge arrays of the relabelled graph alone take 40 bytes
+    // per edge and 32 per vertex; larger graphs are rejected before any work
+    const i64 n = g->n_u + g->n_v;
+    if ((u64)(40 * g->m + 32 * n) > PBNG_SCRATCH_BYTES)
+        return fail(c, PBNG_E_OVERFLOW, "graph too large for the no-allocation scratch of " +
+                                            std::to_string(PBNG_SCRATCH_BYTES >> 20) + " MiB");
+    if (!c.scratch) return fail(c, PBNG_E_DEVICE, "no scratch address on this device");
+    CallScope scope(c);
+    // every block of this call comes from the scratch array (declared after
+    // the call scope, so the fixed region is left before the arena's release)
+    struct Fixed {
+        Arena &a;
+        Fixed(Arena &aa, void *base) : a(aa) {
+            a.fixed_base = static_cast<char *>(base);
+            a.fixed_cap = PBNG_SCRATCH_BYTES;
+            a.fixed_used = 0;
+        }
+        ~Fixed() {
+            a.fixed_base = nullptr;
+            a.fixed_cap = a.fixed_used = 0;
+        }
+    } fixed(c.arena, c.scratch);
+    pbng_opts o = default_opts(opts);
+    o.flags &= ~PBNG_F_KERNEL_TIMING;  // timing events are created on demand
+    return guarded(c, [&] {
+        auto t0 = std::chrono::steady_clock::now();
+        c.timing_begin_call(false);
+        DevGraph G;
+        build_graph(c, *g, G);
+        PBNG_HIP(hipStreamSynchronize(c.stream));
+        c.stats.ms_prep = ms_since(t0);
+        auto t1 = std::chrono::steady_clock::now();
+        if (kind == PBNG_COUNT_EDGE) {
+            CountOut co;
+            co.sup_edge = out;
+            count_butterflies(c, G, co, o);
+        } else {
+            const u64 w = count_side(c, G, kind == PBNG_COUNT_VERTEX_U ? 0 : 1, o, out);
+            c.stats.wedges_count += w;
+            c.stats.wedges += w;
+        }
+        PBNG_HIP(hipStreamSynchronize(c.stream));
+        c.stats.ms_count = ms_since(t1);
         c.stats.ms_total = ms_since(t0);
     });
 }

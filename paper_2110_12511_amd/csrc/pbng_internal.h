@@ -45,10 +45,16 @@ struct Arena {
     std::multimap<size_t, void *> free_blocks;
     std::vector<std::pair<void *, size_t>> in_use;
     size_t bytes_held = 0;
+    // Fixed region: while fixed_base is set, take() carves blocks out of
+    // [fixed_base, fixed_base + fixed_cap) by bumping fixed_used, never
+    // allocates, and throws PBNG_E_NOMEM once the region is exhausted.
+    char *fixed_base = nullptr;
+    size_t fixed_cap = 0, fixed_used = 0;
     void *take(size_t bytes);
     void release_all();  // back to the free list (end of a call)
-    size_t mark() const { return in_use.size(); }
+    size_t mark() const { return fixed_base ? fixed_used : in_use.size(); }
     void release_to(size_t mark);  // blocks taken after `mark` back to the free list
+    size_t fixed_left() const { return fixed_base ? fixed_cap - fixed_used : ~size_t(0); }
     void destroy();      // hipFree everything
 };
 
@@ -82,6 +88,9 @@ struct Ctx {
     // stream used only to capture round graphs (replayed on `stream`)
     hipStream_t cap_stream = nullptr;
     hipStream_t capture_stream();
+    // device address of the library's static scratch array on this
+    // context's device (pbng_count_noalloc)
+    void *scratch = nullptr;
     // schedule outputs of a tip call (device pointers, set by
     // pbng_tip_schedule for one call): partition of each vertex, support at
     // its partition's start, exclusive upper bound of each partition

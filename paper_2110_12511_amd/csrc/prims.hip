@@ -9,6 +9,15 @@ namespace pbng {
 
 void *Arena::take(size_t bytes) {
     bytes = (bytes + 255) & ~size_t(255);
+    if (fixed_base) {
+        if (bytes > fixed_cap - fixed_used)
+            throw Error(PBNG_E_NOMEM, "the no-allocation scratch of " + std::to_string(fixed_cap >> 20) +
+                                          " MiB is too small for this graph (" + std::to_string(fixed_used + bytes) +
+                                          " bytes needed so far)");
+        void *p = fixed_base + fixed_used;
+        fixed_used += bytes;
+        return p;
+    }
     auto it = free_blocks.lower_bound(bytes);
     if (it != free_blocks.end() && it->first <= 2 * bytes + (64u << 20)) {
         void *p = it->second;
@@ -38,11 +47,16 @@ void *Arena::take(size_t bytes) {
 }
 
 void Arena::release_all() {
+    fixed_used = 0;
     for (auto &b : in_use) free_blocks.insert({b.second, b.first});
     in_use.clear();
 }
 
 void Arena::release_to(size_t mark) {
+    if (fixed_base) {
+        if (mark < fixed_used) fixed_used = mark;
+        return;
+    }
     while (in_use.size() > mark) {
         free_blocks.insert({in_use.back().second, in_use.back().first});
         in_use.pop_back();
