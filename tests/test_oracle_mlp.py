@@ -1,5 +1,6 @@
 """Pins of the predictor oracle (oracle/mlp.py) to facts outside itself:
-finite differences for the gradient, hand-built networks with known outputs,
+finite differences for the gradient, hand-built networks with known outputs
+and a hand-computed loss,
 Adam's bias-corrected steps under a constant gradient, and closed-form
 features of complete bipartite graphs."""
 import math
@@ -52,6 +53,25 @@ def test_forward_constant_network():
     X, _, _ = rand_data(5, 3)
     y, _ = mlp.forward(p, X)
     assert np.allclose(y, 1 / (1 + math.exp(-0.7)))
+
+
+@pytest.mark.parametrize("b4,expected", [(0.0, 1.0 / 15.0), (math.log(3.0), 2.1875 / 15.0)])
+def test_loss_of_constant_network(b4, expected):
+    """A network whose only nonzero parameter is the output bias predicts
+    sigmoid(b4) for every row: 0.5 at b4 = 0 and 0.75 at b4 = ln 3.  With
+    labels (0, 1, 1/4, 1/2) and row weights (1, 2, 4, 8) the weighted mean
+    squared error is, by hand, (1/4 + 2/4 + 4/16 + 0) / 15 = 1/15 and
+    (9/16 + 2/16 + 4/4 + 8/16) / 15 = 2.1875/15.  An unweighted mean (1/4),
+    an absolute error (2.5/15) or a sum without the division would differ."""
+    p = np.zeros(mlp.NPARAM)
+    p[-1] = b4
+    X = np.random.default_rng(4).uniform(-1, 2, size=(4, mlp.IN))
+    Y = np.array([0.0, 1.0, 0.25, 0.5])
+    Wt = np.array([1.0, 2.0, 4.0, 8.0])
+    assert mlp.loss(p, X, Y, Wt) == pytest.approx(expected, rel=1e-12)
+    assert mlp.loss_grad(p, X, Y, Wt)[0] == pytest.approx(expected, rel=1e-12)
+    # the loss is a weighted mean: scaling every weight leaves it unchanged
+    assert mlp.loss(p, X, Y, 3.0 * Wt) == pytest.approx(expected, rel=1e-12)
 
 
 def test_forward_hand_built_path():
