@@ -94,11 +94,13 @@ typedef enum {
 #define PBNG_F_NO_DENSE_TILE 0x4 /* counting: scalar path for hub pairs too */
 #define PBNG_F_KERNEL_TIMING 0x8 /* time kernel classes with HIP events on
                                     the context stream (fills
-                                    pbng_stats.kstat)                       */
-#define PBNG_F_HOST_ROUNDS 0x10  /* wing: coarse-grained rounds driven from
-                                    the host, one synchronisation per round,
-                                    instead of replays of a captured HIP
-                                    graph of several rounds                  */
+                                    pbng_stats.kstat); coarse-grained tip
+                                    rounds are then driven from the host    */
+#define PBNG_F_HOST_ROUNDS 0x10  /* tip and wing: coarse-grained rounds
+                                    driven from the host, one
+                                    synchronisation per round, instead of
+                                    replays of a captured HIP graph of
+                                    several rounds                           */
 
 /* Kernel classes timed under PBNG_F_KERNEL_TIMING. */
 enum {

@@ -107,10 +107,12 @@ struct Ctx {
         return static_cast<T *>(arena.take((n ? n : 1) * sizeof(T)));
     }
     hipEvent_t event();
-    void kbegin(int cls);
-    void kend(int cls);
+    // interval of kernel class cls on stream st (the context stream if null)
+    void kbegin(int cls, hipStream_t st = nullptr);
+    void kend(int cls, hipStream_t st = nullptr);
     void timing_begin_call(bool on);
     void timing_end_call();  // fills stats.kstat (synchronises)
+
 };
 
 // Graph in device memory after preprocessing (Algorithm 1, priority

@@ -129,16 +129,16 @@ hipStream_t Ctx::aux() {
     return aux_stream;
 }
 
-void Ctx::kbegin(int cls) {
+void Ctx::kbegin(int cls, hipStream_t st) {
     if (!timing) return;
     hipEvent_t a = event(), b = event();
-    PBNG_HIP(hipEventRecord(a, stream));
+    PBNG_HIP(hipEventRecord(a, st ? st : stream));
     intervals[cls].push_back({a, b});
 }
 
-void Ctx::kend(int cls) {
+void Ctx::kend(int cls, hipStream_t st) {
     if (!timing) return;
-    PBNG_HIP(hipEventRecord(intervals[cls].back().second, stream));
+    PBNG_HIP(hipEventRecord(intervals[cls].back().second, st ? st : stream));
 }
 
 void Ctx::timing_begin_call(bool on) {

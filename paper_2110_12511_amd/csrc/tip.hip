@@ -49,9 +49,21 @@ struct TipCtl {
     u32 nbin[5];    // active-set bins: small, medium, hash ranges, key tiles, pair intersections
     u32 next[5];    // work counters
     u32 ndirty;     // Y lists to compact
-    u32 pad;
+    i32 pid;        // current partition
     u64 tnext;      // work counter of the key-tile items (vertex x tile)
+    u64 alive;      // vertices neither active nor peeled, before the round
+    u64 wbound;     // recount bound on an active set's wedges (Section 5.1)
+    u64 rounds;     // rounds with a nonempty active set (captured rounds)
+    u32 recount;    // a captured round handed its active set to a recount
+    u32 pad2;
 };
+
+// Captured coarse-grained rounds: a HIP graph of TIP_GRAPH_K rounds (even,
+// so the current and next active-set buffers are back in place after a
+// replay) is replayed until a partition's active set is empty.  Most
+// partitions take two rounds: the one the frontier starts and a short one
+// for the vertices it pushes below the bound.
+constexpr int TIP_GRAPH_K = 2;
 
 // Heavy active vertices accumulate c(x, x') in LDS over key tiles of
 // 2^TILE_LOG consecutive X ids, two 16-bit counters per 32-bit word, or of
@@ -179,8 +191,10 @@ __device__ __forceinline__ void run_ends(const i32 *yadj, const i32 *pre, const 
         if (k0 + q >= tot) xq[q] = x;
 }
 
-// next active set of a push round: alive vertices below the bound
+// next active set of a push round: alive vertices below the bound (none
+// when the round had no active set)
 __global__ void k_sweep_frontier(const unsigned char *st, const u64 *sup, const TipCtl *ctl, i64 nx, i32 *nf, u32 *nnf) {
+    if (ctl->nF == 0) return;
     const u64 B = ctl->bound;
     const i64 stride = (i64)gridDim.x * blockDim.x;
     const i64 nn = (nx + WAVE - 1) / WAVE * WAVE;
@@ -823,8 +837,9 @@ __global__ __launch_bounds__(256) void k_part_work(const unsigned char *st, cons
     if (threadIdx.x == 0 && t) atomicAdd((unsigned long long *)&ctl->est_final, (unsigned long long)t);
 }
 
-__global__ void k_activate(const i32 *F2, const u32 *nF2, unsigned char *st, i32 *part, i32 pid) {
+__global__ void k_activate(const i32 *F2, const u32 *nF2, unsigned char *st, i32 *part, const TipCtl *ctl) {
     const u32 n = *nF2;
+    const i32 pid = ctl->pid;
     for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) {
         i32 x = F2[i];
         st[x] = ST_ACTIVE;
@@ -896,8 +911,9 @@ __global__ void k_learned_guard(TipCtl *ctl, const u64 *mn) {
     if (ctl->s < mn[0]) ctl->s = mn[0];
 }
 
-__global__ void k_set_bound(TipCtl *ctl, int last) {
+__global__ void k_set_bound(TipCtl *ctl, int last, i32 pid) {
     ctl->bound = last ? ~0ull : ctl->s + 1;
+    ctl->pid = pid;
     ctl->nF = 0;
     ctl->nF2 = 0;
     ctl->wF = 0;
@@ -907,6 +923,23 @@ __global__ void k_set_bound(TipCtl *ctl, int last) {
 }
 
 __global__ void k_record_bound(const TipCtl *ctl, u64 *out) { *out = ctl->bound; }
+
+// Start of a captured round: an empty active set makes the round a no-op
+// (every kernel finds nothing to do).  An active set holding every alive
+// vertex needs no updates, and one whose wedges exceed the recount bound is
+// handed to a recount after the replay (Section 5.1): both empty the work
+// bins so the round only retires the set.
+__global__ void k_round_begin(TipCtl *ctl, int batch) {
+    const u32 nF = ctl->nF;
+    if (nF == 0) return;
+    ctl->rounds += 1;
+    const bool all = (u64)nF == ctl->alive;
+    const bool rec = !all && batch && ctl->wF > ctl->wbound;
+    if (all || rec)
+        for (int b = 0; b < 5; ++b) ctl->nbin[b] = 0;
+    if (rec) ctl->recount = 1;
+    ctl->alive -= nF;
+}
 
 __global__ void k_next_round(TipCtl *ctl) {
     // next active set becomes current; counters of the round are cleared
@@ -1644,6 +1677,122 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
         paper_rule || o.level_alive < 0 ? -1 : (o.level_alive > 0 ? (i64)o.level_alive : LEVEL_MAX_ALIVE);
     const u64 level_min_work = o.level_alive > 0 ? 0 : LEVEL_MIN_WORK;
     const u64 level_min_avg = o.level_alive > 0 ? 0 : LEVEL_MIN_AVG;
+    // ---- coarse-grained rounds
+    // A push round peels the current active set Fa by wedge traversal and
+    // sweeps the next one into Fb; gridF bounds the grids (the active set's
+    // size on the host-driven path, every vertex when captured).
+    auto push_round = [&](hipStream_t rs, i32 *Fa, i32 *Fb, i64 gridF) {
+        (void)Fa;
+        pa.items = bins;
+        pa.nf = Fb;
+        PeelArgs pd = pa;
+        pd.items = bins + 3 * nx;
+        PeelArgs pt = pa;
+        pt.items = bins + 2 * nx;
+        PeelArgs pm = pa;
+        pm.items = bins + nx;
+        {
+            PeelArgs pk = pd;
+            pk.kc = c.kctr + PBNG_K_TIP_TILED;
+            c.kbegin(PBNG_K_TIP_TILED, rs);
+            const dim3 tg((unsigned)std::min<i64>(tslots, gridF * ntiles));
+            if (pack16)
+                hipLaunchKernelGGL((k_tip_peel_tiled<TILE_LOG, true>), tg, dim3(512), 0, rs, pk, 3);
+            else
+                hipLaunchKernelGGL((k_tip_peel_tiled<TILE_LOG - 1, false>), tg, dim3(512), 0, rs, pk, 3);
+            c.kend(PBNG_K_TIP_TILED, rs);
+        }
+        c.kbegin(PBNG_K_TIP_PEEL, rs);
+        hipLaunchKernelGGL(k_range_split, dim3(1), dim3(1024), 0, rs, (const i32 *)pt.items, (const u32 *)ctl->nbin, 2,
+                           (const u64 *)wi, hoff, htotal);
+        c.kend(PBNG_K_TIP_PEEL, rs);
+        {
+            PeelArgs ph = pt;
+            ph.kc = c.kctr + PBNG_K_TIP_HRANGE;
+            c.kbegin(PBNG_K_TIP_HRANGE, rs);
+            hipLaunchKernelGGL(k_tip_peel_hrange<H_LOGCAP>, dim3(std::min<i64>(slots, gridF * H_RANGE_MAX)), dim3(512), 0, rs,
+                               ph, 2, (const u32 *)hoff, (const u32 *)htotal);
+            c.kend(PBNG_K_TIP_HRANGE, rs);
+        }
+        c.kbegin(PBNG_K_TIP_PEEL, rs);
+        {
+            PeelArgs pp = pa;
+            pp.items = bins + 4 * nx;
+            hipLaunchKernelGGL(k_tip_peel_pairs, dim3(std::min<i64>((i64)c.num_cu * 8, (gridF + 3) / 4)), dim3(256), 0, rs, pp,
+                               4);
+        }
+        hipLaunchKernelGGL((k_tip_peel_hash<256, 13>), dim3(std::min<i64>((i64)c.num_cu * 2, gridF)), dim3(256), 0, rs, pm, 1);
+        hipLaunchKernelGGL((k_tip_peel_hash<64, 10>), dim3(std::min<i64>((i64)c.num_cu * 16, gridF)), dim3(64), 0, rs, pa, 0);
+        c.kend(PBNG_K_TIP_PEEL, rs);
+        PBNG_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_sweep_frontier, dim3(gx), dim3(256), 0, rs, (const unsigned char *)st, (const u64 *)sup,
+                           (const TipCtl *)ctl, nx, Fb, &ctl->nF2);
+        PBNG_LAUNCH_CHECK();
+    };
+    // after the updates: retire Fa, activate Fb, compact the dirty lists,
+    // make Fb current and bin it
+    // (grid-stride kernels; captured rounds launch at most gcap blocks)
+    auto end_round = [&](hipStream_t rs, i32 *Fa, i32 *Fb, i64 gridF, int gcap) {
+        hipLaunchKernelGGL(k_retire, dim3(grid_1d(gridF * WAVE, 256, gcap)), dim3(256), 0, rs, (const i32 *)Fa,
+                           (const u32 *)&ctl->nF, xrow, xadj, st, ydeg, ydirty, dirty, &ctl->ndirty, dynamic ? 1 : 0);
+        hipLaunchKernelGGL(k_activate, dim3(grid_1d(nx, 256, gcap)), dim3(256), 0, rs, (const i32 *)Fb, (const u32 *)&ctl->nF2,
+                           st, part, (const TipCtl *)ctl);
+        PBNG_LAUNCH_CHECK();
+        if (dynamic) {
+            hipLaunchKernelGGL(k_compact, dim3(grid_1d((i64)ny * WAVE, 256, gcap)), dim3(256), 0, rs, (const i32 *)dirty,
+                               (const u32 *)&ctl->ndirty, yrow, yadj, ylen, ydirty, (const unsigned char *)st);
+            PBNG_LAUNCH_CHECK();
+        }
+        hipLaunchKernelGGL(k_next_round, dim3(1), dim3(1), 0, rs, ctl);
+        hipLaunchKernelGGL(k_item_work, dim3(grid_1d((i64)nx * WAVE, 256, gcap)), dim3(256), 0, rs, (const i32 *)Fb,
+                           (const u32 *)&ctl->nF, xrow, xadj, (const i32 *)ylen, wi, &ctl->wF, bins, nx, ctl->nbin, huge_w);
+        PBNG_LAUNCH_CHECK();
+    };
+    // Section 5.1: supports of the remaining graph by counting (the active
+    // set is already retired), then the active set below the bound
+    auto recount_remaining = [&]() {
+        hipLaunchKernelGGL(k_alive_label, dim3(grid_1d(G.n)), dim3(256), 0, s, (const unsigned char *)st, (const i32 *)G.gid,
+                           G.n, xoff, nx, alive_label);
+        PBNG_LAUNCH_CHECK();
+        recount_wedges += count_pass(c, G, sup_label, nullptr, alive_label);
+        hipLaunchKernelGGL(k_from_label, dim3(gx), dim3(256), 0, s, (const u64 *)sup_label, (const i32 *)G.label, xoff, nx,
+                           (const unsigned char *)st, sup);
+        PBNG_LAUNCH_CHECK();
+        ++recounts;
+        hipLaunchKernelGGL(k_frontier, dim3(gx), dim3(256), 0, s, st, (const u64 *)sup, (const u64 *)w, init, wsnap, part, nx,
+                           ctl, pid, 0, F);
+        PBNG_LAUNCH_CHECK();
+        item_work(F);
+    };
+    // captured rounds; host-driven with PBNG_F_HOST_ROUNDS, while tracing,
+    // and under kernel-class timing (events recorded inside a graph cannot
+    // be timed here: kernels are the same either way)
+    const bool host_rounds = (o.flags & (PBNG_F_HOST_ROUNDS | PBNG_F_KERNEL_TIMING)) != 0 || trace;
+    GraphExec rounds_exec;
+    {
+        const u64 init_ctl[2] = {(u64)nx, wedge_cnt_bound};  // alive, wbound
+        PBNG_HIP(hipMemcpyAsync(&ctl->alive, init_ctl, sizeof(init_ctl), hipMemcpyHostToDevice, s));
+    }
+    if (!host_rounds) {
+        hipStream_t cs = c.capture_stream();
+        PBNG_HIP(hipStreamSynchronize(s));
+        PBNG_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        i32 *Fa = F, *Fb = F2;
+        for (int r = 0; r < TIP_GRAPH_K; ++r) {
+            hipLaunchKernelGGL(k_round_begin, dim3(1), dim3(1), 0, cs, ctl, batch ? 1 : 0);
+            push_round(cs, Fa, Fb, c.num_cu * 4);
+            end_round(cs, Fa, Fb, nx, c.num_cu * 8);
+            std::swap(Fa, Fb);
+        }
+        const hipError_t le = hipGetLastError();
+        hipGraph_t graph = nullptr;
+        const hipError_t ee = hipStreamEndCapture(cs, &graph);
+        PBNG_HIP(le);
+        PBNG_HIP(ee);
+        const hipError_t ie = hipGraphInstantiate(&rounds_exec.e, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        PBNG_HIP(ie);
+    }
     while (n_alive > 0) {
         const bool at_last = (P - pid) <= 1;
         // work estimate of every alive vertex with the current live degrees
@@ -1704,133 +1853,84 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
                                 cnt_target);
             }
         }
-        hipLaunchKernelGGL(k_set_bound, dim3(1), dim3(1), 0, s, ctl, last ? 1 : 0);
+        hipLaunchKernelGGL(k_set_bound, dim3(1), dim3(1), 0, s, ctl, last ? 1 : 0, (i32)pid);
         if (pbound) hipLaunchKernelGGL(k_record_bound, dim3(1), dim3(1), 0, s, (const TipCtl *)ctl, pbound + pid);
         hipLaunchKernelGGL(k_frontier, dim3(gx), dim3(256), 0, s, st, (const u64 *)sup, (const u64 *)w, init, wsnap, part,
                            nx, ctl, pid, 1, F);
         PBNG_LAUNCH_CHECK();
         item_work(F);
-        HostView hv;
-        PBNG_HIP(hipMemcpyAsync(&hv.nF, &ctl->nF, sizeof(u32), hipMemcpyDeviceToHost, s));
-        PBNG_HIP(hipMemcpyAsync(&hv.wF, &ctl->wF, sizeof(u64), hipMemcpyDeviceToHost, s));
-        PBNG_HIP(hipStreamSynchronize(s));
-        while (hv.nF > 0) {
-            ++rho;
-            const u32 nF = hv.nF;
-            const int gw = grid_1d((i64)nF * WAVE);
-            if ((i64)nF == n_alive) {
-                // everything left joins this partition: no updates needed
-                hipLaunchKernelGGL(k_retire, dim3(gw), dim3(256), 0, s, (const i32 *)F, (const u32 *)&ctl->nF, xrow, xadj, st,
-                                   ydeg, ydirty, dirty, &ctl->ndirty, 0);
-                PBNG_LAUNCH_CHECK();
-                n_alive = 0;
-                hipLaunchKernelGGL(k_next_round, dim3(1), dim3(1), 0, s, ctl);
-                break;
+        if (!host_rounds) {
+            // replays until the partition's active set is empty; a replay
+            // that handed a set to a recount is followed by the recount here
+            for (;;) {
+                PBNG_HIP(hipGraphLaunch(rounds_exec.e, s));
+                TipCtl h;
+                PBNG_HIP(hipMemcpyAsync(&h, ctl, sizeof(TipCtl), hipMemcpyDeviceToHost, s));
+                PBNG_HIP(hipStreamSynchronize(s));
+                n_alive = (i64)h.alive;
+                if (h.recount) {
+                    recount_remaining();
+                    const u32 zero = 0;
+                    PBNG_HIP(hipMemcpyAsync(&ctl->recount, &zero, sizeof(u32), hipMemcpyHostToDevice, s));
+                    continue;
+                }
+                if (h.nF == 0) break;
             }
-            if (batch && hv.wF > wedge_cnt_bound) {
-                // Section 5.1: recount the remaining graph instead of peeling
-                hipLaunchKernelGGL(k_retire, dim3(gw), dim3(256), 0, s, (const i32 *)F, (const u32 *)&ctl->nF, xrow, xadj, st,
-                                   ydeg, ydirty, dirty, &ctl->ndirty, dynamic ? 1 : 0);
-                hipLaunchKernelGGL(k_alive_label, dim3(grid_1d(G.n)), dim3(256), 0, s, (const unsigned char *)st,
-                                   (const i32 *)G.gid, G.n, xoff, nx, alive_label);
-                PBNG_LAUNCH_CHECK();
-                recount_wedges += count_pass(c, G, sup_label, nullptr, alive_label);
-                hipLaunchKernelGGL(k_from_label, dim3(gx), dim3(256), 0, s, (const u64 *)sup_label, (const i32 *)G.label, xoff,
-                                   nx, (const unsigned char *)st, sup);
-                PBNG_LAUNCH_CHECK();
-                ++recounts;
-                n_alive -= nF;
-                if (dynamic) {
-                    hipLaunchKernelGGL(k_compact, dim3(grid_1d((i64)ny * WAVE)), dim3(256), 0, s, (const i32 *)dirty,
-                                       (const u32 *)&ctl->ndirty, yrow, yadj, ylen, ydirty, (const unsigned char *)st);
-                    PBNG_LAUNCH_CHECK();
-                }
-                hipLaunchKernelGGL(k_next_round, dim3(1), dim3(1), 0, s, ctl);
-                hipLaunchKernelGGL(k_frontier, dim3(gx), dim3(256), 0, s, st, (const u64 *)sup, (const u64 *)w, init, wsnap,
-                                   part, nx, ctl, pid, 0, F);
-                PBNG_LAUNCH_CHECK();
-                item_work(F);
-            } else {
-                pa.items = bins;
-                pa.nf = F2;
-                PeelArgs pd = pa;
-                pd.items = bins + 3 * nx;
-                PeelArgs pt = pa;
-                pt.items = bins + 2 * nx;
-                PeelArgs pm = pa;
-                pm.items = bins + nx;
-                c.kbegin(PBNG_K_TIP_PEEL);
-                {
-                    c.kend(PBNG_K_TIP_PEEL);
-                    PeelArgs pk = pd;
-                    pk.kc = c.kctr + PBNG_K_TIP_TILED;
-                    c.kbegin(PBNG_K_TIP_TILED);
-                    const dim3 tg((unsigned)std::min<i64>(tslots, (i64)nF * ntiles));
-                    if (pack16)
-                        hipLaunchKernelGGL((k_tip_peel_tiled<TILE_LOG, true>), tg, dim3(512), 0, s, pk, 3);
-                    else
-                        hipLaunchKernelGGL((k_tip_peel_tiled<TILE_LOG - 1, false>), tg, dim3(512), 0, s, pk, 3);
-                    c.kend(PBNG_K_TIP_TILED);
-                    c.kbegin(PBNG_K_TIP_PEEL);
-                }
-                hipLaunchKernelGGL(k_range_split, dim3(1), dim3(1024), 0, s, (const i32 *)pt.items, (const u32 *)ctl->nbin, 2,
-                                   (const u64 *)wi, hoff, htotal);
-                c.kend(PBNG_K_TIP_PEEL);
-                {
-                    PeelArgs ph = pt;
-                    ph.kc = c.kctr + PBNG_K_TIP_HRANGE;
-                    c.kbegin(PBNG_K_TIP_HRANGE);
-                    hipLaunchKernelGGL(k_tip_peel_hrange<H_LOGCAP>, dim3(std::min<i64>(slots, (i64)nF * H_RANGE_MAX)), dim3(512),
-                                       0, s, ph, 2, (const u32 *)hoff, (const u32 *)htotal);
-                    c.kend(PBNG_K_TIP_HRANGE);
-                }
-                c.kbegin(PBNG_K_TIP_PEEL);
-                {
-                    PeelArgs pp = pa;
-                    pp.items = bins + 4 * nx;
-                    hipLaunchKernelGGL(k_tip_peel_pairs, dim3(std::min<i64>((i64)c.num_cu * 8, ((i64)nF + 3) / 4)), dim3(256), 0,
-                                       s, pp, 4);
-                }
-                hipLaunchKernelGGL((k_tip_peel_hash<256, 13>), dim3(std::min<i64>((i64)c.num_cu * 2, nF)), dim3(256), 0, s, pm, 1);
-                hipLaunchKernelGGL((k_tip_peel_hash<64, 10>), dim3(std::min<i64>((i64)c.num_cu * 16, nF)), dim3(64), 0, s, pa, 0);
-                c.kend(PBNG_K_TIP_PEEL);
-                PBNG_LAUNCH_CHECK();
-                hipLaunchKernelGGL(k_sweep_frontier, dim3(gx), dim3(256), 0, s, (const unsigned char *)st, (const u64 *)sup,
-                                   (const TipCtl *)ctl, nx, F2, &ctl->nF2);
-                PBNG_LAUNCH_CHECK();
-            }
-            if (!(batch && hv.wF > wedge_cnt_bound)) {
-                if (trace) {
-                    u32 nb[4];
-                    u64 wtot;
-                    PBNG_HIP(hipMemcpyAsync(nb, ctl->nbin, sizeof(nb), hipMemcpyDeviceToHost, s));
-                    PBNG_HIP(hipMemcpyAsync(&wtot, &ctl->wedges, sizeof(u64), hipMemcpyDeviceToHost, s));
-                    PBNG_HIP(hipStreamSynchronize(s));
-                    double tnow = now_ms();
-                    fprintf(stderr, "[pbng-trace] part %d round %llu nF %u wF %llu bins %u/%u/%u/%u wedges %llu ms %.3f\n",
-                            pid, (unsigned long long)rho, nF, (unsigned long long)hv.wF, nb[0], nb[1], nb[2], nb[3],
-                            (unsigned long long)(wtot - trace_w), tnow - trace_t);
-                    trace_w = wtot;
-                    trace_t = tnow;
-                }
-                hipLaunchKernelGGL(k_retire, dim3(gw), dim3(256), 0, s, (const i32 *)F, (const u32 *)&ctl->nF, xrow, xadj, st,
-                                   ydeg, ydirty, dirty, &ctl->ndirty, dynamic ? 1 : 0);
-                hipLaunchKernelGGL(k_activate, dim3(grid_1d(nx)), dim3(256), 0, s, (const i32 *)F2, (const u32 *)&ctl->nF2, st,
-                                   part, pid);
-                PBNG_LAUNCH_CHECK();
-                if (dynamic) {
-                    hipLaunchKernelGGL(k_compact, dim3(grid_1d((i64)ny * WAVE)), dim3(256), 0, s, (const i32 *)dirty,
-                                       (const u32 *)&ctl->ndirty, yrow, yadj, ylen, ydirty, (const unsigned char *)st);
-                    PBNG_LAUNCH_CHECK();
-                }
-                n_alive -= nF;
-                hipLaunchKernelGGL(k_next_round, dim3(1), dim3(1), 0, s, ctl);
-                std::swap(F, F2);
-                item_work(F);
-            }
+        } else {
+            HostView hv;
             PBNG_HIP(hipMemcpyAsync(&hv.nF, &ctl->nF, sizeof(u32), hipMemcpyDeviceToHost, s));
             PBNG_HIP(hipMemcpyAsync(&hv.wF, &ctl->wF, sizeof(u64), hipMemcpyDeviceToHost, s));
             PBNG_HIP(hipStreamSynchronize(s));
+            while (hv.nF > 0) {
+                ++rho;
+                const u32 nF = hv.nF;
+                const int gw = grid_1d((i64)nF * WAVE);
+                if ((i64)nF == n_alive) {
+                    // everything left joins this partition: no updates needed
+                    hipLaunchKernelGGL(k_retire, dim3(gw), dim3(256), 0, s, (const i32 *)F, (const u32 *)&ctl->nF, xrow, xadj,
+                                       st, ydeg, ydirty, dirty, &ctl->ndirty, 0);
+                    PBNG_LAUNCH_CHECK();
+                    n_alive = 0;
+                    hipLaunchKernelGGL(k_next_round, dim3(1), dim3(1), 0, s, ctl);
+                    break;
+                }
+                if (batch && hv.wF > wedge_cnt_bound) {
+                    // Section 5.1: recount the remaining graph instead of peeling
+                    hipLaunchKernelGGL(k_retire, dim3(gw), dim3(256), 0, s, (const i32 *)F, (const u32 *)&ctl->nF, xrow, xadj,
+                                       st, ydeg, ydirty, dirty, &ctl->ndirty, dynamic ? 1 : 0);
+                    PBNG_LAUNCH_CHECK();
+                    n_alive -= nF;
+                    if (dynamic) {
+                        hipLaunchKernelGGL(k_compact, dim3(grid_1d((i64)ny * WAVE)), dim3(256), 0, s, (const i32 *)dirty,
+                                           (const u32 *)&ctl->ndirty, yrow, yadj, ylen, ydirty, (const unsigned char *)st);
+                        PBNG_LAUNCH_CHECK();
+                    }
+                    hipLaunchKernelGGL(k_next_round, dim3(1), dim3(1), 0, s, ctl);
+                    recount_remaining();
+                } else {
+                    push_round(s, F, F2, nF);
+                    if (trace) {
+                        u32 nb[4];
+                        u64 wtot;
+                        PBNG_HIP(hipMemcpyAsync(nb, ctl->nbin, sizeof(nb), hipMemcpyDeviceToHost, s));
+                        PBNG_HIP(hipMemcpyAsync(&wtot, &ctl->wedges, sizeof(u64), hipMemcpyDeviceToHost, s));
+                        PBNG_HIP(hipStreamSynchronize(s));
+                        double tnow = now_ms();
+                        fprintf(stderr,
+                                "[pbng-trace] part %d round %llu nF %u wF %llu bins %u/%u/%u/%u wedges %llu ms %.3f\n", pid,
+                                (unsigned long long)rho, nF, (unsigned long long)hv.wF, nb[0], nb[1], nb[2], nb[3],
+                                (unsigned long long)(wtot - trace_w), tnow - trace_t);
+                        trace_w = wtot;
+                        trace_t = tnow;
+                    }
+                    end_round(s, F, F2, nF, 16384);
+                    n_alive -= nF;
+                    std::swap(F, F2);
+                }
+                PBNG_HIP(hipMemcpyAsync(&hv.nF, &ctl->nF, sizeof(u32), hipMemcpyDeviceToHost, s));
+                PBNG_HIP(hipMemcpyAsync(&hv.wF, &ctl->wF, sizeof(u64), hipMemcpyDeviceToHost, s));
+                PBNG_HIP(hipStreamSynchronize(s));
+            }
         }
         hipLaunchKernelGGL(k_part_work, dim3(std::min<i64>(grid_1d(nx), 512)), dim3(256), 0, s, (const unsigned char *)st,
                            (const i32 *)part, (const u64 *)wsnap, nx, pid, ctl);
@@ -1840,6 +1940,7 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
     }
     const i32 np = pid;
     c.stats.wedges_cd = read_scalar<u64>(c, &ctl->wedges) + recount_wedges;
+    if (!host_rounds) rho += read_scalar<u64>(c, &ctl->rounds);
     c.stats.rho = rho;
     c.stats.recounts = recounts;
     c.stats.partitions = np;

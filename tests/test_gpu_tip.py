@@ -141,6 +141,27 @@ def test_tip_recount_rounds(ctx, cl_mid, P):
         assert np.array_equal(gpu_tip(ctx, gs, 0, P=3, recount_w=1), oracle.tip(gs, 0))
 
 
+@pytest.mark.parametrize("P", [1, 7, 150])
+def test_tip_host_rounds_match_captured(ctx, cl_mid, P):
+    """Coarse-grained rounds replayed from a captured HIP graph and rounds
+    driven from the host give the oracle's numbers in the same number of
+    rounds."""
+    g, eu, ev = cl_mid
+    for side, exp in ((0, eu), (1, ev)):
+        a = gpu_tip(ctx, g, side, P=P)
+        ra = ctx.stats()["rho"]
+        b = gpu_tip(ctx, g, side, P=P, flags=pb.F_HOST_ROUNDS)
+        rb = ctx.stats()["rho"]
+        assert np.array_equal(a, exp) and np.array_equal(b, exp)
+        assert ra == rb, (side, ra, rb)
+
+
+def test_tip_recount_rounds_host_driven(ctx, cl_mid):
+    g, eu, _ = cl_mid
+    assert np.array_equal(gpu_tip(ctx, g, 0, P=7, recount_w=1, flags=pb.F_HOST_ROUNDS), eu)
+    assert ctx.stats()["recounts"] > 0
+
+
 def test_tip_paper_rule(ctx, cl_mid):
     """The paper's bound rule alone (no vertex-count target, no single
     levels) gives the same numbers."""
