@@ -1,16 +1,20 @@
 #!/usr/bin/env python3
 """Benchmark of the MI355X butterfly-peeling path.
 
-A step is one tip decomposition of both sides (U, then V) of the seeded
-Chung-Lu workload |U|=1M, |V|=200k, 20M edges, exponent 2.1, degree cap 50k,
-P=150, plain bound rule: preprocessing, priority counting, coarse-grained
-peel rounds (with recounts) and the fine-grained persistent kernel, all on the
-GPU with the graph resident in HBM before the timed region.
+Default workload: tip decomposition of side U of the seeded Chung-Lu graph
+|U|=5M, |V|=1M, 100M edges, exponent 2.0, degree cap 50k, P=150 -- the
+held-out graph on which learned and plain range bounds are compared.  A step
+is one call: preprocessing, priority counting, coarse-grained peel rounds
+(replayed from a captured HIP graph, with recounts) and the fine-grained
+persistent kernel, all on the GPU with the graph resident in HBM before the
+timed region.
 
-Prints one JSON line: wedges/s over the whole step (value), the per-step
-decomposition time, the roofline of the dominant kernel class (algorithmic
-bytes / its HIP-event time on the library's stream), and the CPU oracle timed
-on a bounded sample of the same workload family.
+Prints one JSON line: wedges/s over the timed steps (value), the per-step
+decomposition time, the bound rules compared on the same graph (the library's
+plain rule, the paper's rule alone, learned), the roofline of the dominant
+kernel class (algorithmic bytes / its HIP-event time on the library's stream,
+from a kernel-timing pass), the 20M-edge tip and 5M-edge wing workloads as
+extra keys, and the CPU oracle timed on a bounded sample.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload NAME]
 """
@@ -31,8 +35,8 @@ sys.path.insert(0, ROOT)
 METRIC = "wedges/s + tip/wing decomposition time, learned vs plain CD bounds, 1 GPU"
 HBM_PEAK_GBS = 8000.0
 # kernel behind each timed class that holds a single kernel
-CLASS_KERNEL = {"tip_hrange": "k_tip_peel_hrange<14>", "tip_tiled": "k_tip_peel_tiled<16>", "fd": "k_tip_fd / k_wing_fd",
-                "dense": "m_gram"}
+CLASS_KERNEL = {"tip_hrange": "k_tip_peel_hrange<14>", "tip_tiled": "k_tip_peel_tiled<16, true>",
+                "fd": "k_tip_fd / k_wing_fd", "dense": "m_gram", "wing_cd": "w_links / w_blooms"}
 
 WORKLOADS = {
     # name: (graph config, kind, P); kinds: tip (both sides), tip_u (side U),
@@ -65,9 +69,9 @@ def golden(workload, quantity):
         return json.load(f)
 
 
-def run_step(pb, ctx, dg, kind, P, flags):
+def run_step(pb, ctx, dg, kind, P, flags, rule=0):
     """One pass of the hot path; returns (outputs, list of stats dicts)."""
-    opts = pb.make_opts(P=P, flags=flags)
+    opts = pb.make_opts(P=P, flags=flags, bound_rule=rule)
     outs, stats = [], []
     if kind in ("tip", "tip_u"):
         for side in ((pb.SIDE_U, pb.SIDE_V) if kind == "tip" else (pb.SIDE_U,)):
@@ -129,12 +133,31 @@ def profile_traffic(kernel_class, workload):
     return int(m.group(1))
 
 
+def host_info():
+    """Host core count and CPU model of the machine the oracle runs on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return dict(nproc=os.cpu_count(), cpu_model=model)
+
+
 def cpu_baseline(graph_cfg, kind, budget_s):
     """The oracle on a bounded sample: the same generator family scaled down
-    until one run takes about budget_s seconds on one host core."""
+    until one run takes about budget_s seconds on one host core.  The
+    oracle's counting walks exactly the wedges its peeling walks (every
+    u -> v -> u' with u' != u, peeled u' included), so a tip run's work is
+    twice its peel counter."""
     import oracle
     import synth
 
+    oracle.set_threads(1)
+    info = host_info()
     if kind == "batch":
         # the batch's own graphs in order until the budget is spent
         nb, m_min, m_max = BATCHES[graph_cfg]
@@ -148,7 +171,7 @@ def cpu_baseline(graph_cfg, kind, budget_s):
             k += 1
         return dict(value=wedges / dt if dt > 0 else 0.0, unit="wedges/s", cores=1, kind="oracle",
                     sample=f"the first {k} graphs of the batch: tip side U by sequential bottom-up peeling, "
-                           f"{wedges} wedges in {dt:.2f} s", seconds=round(dt, 2))
+                           f"{wedges} wedges in {dt:.2f} s", seconds=round(dt, 2), **info)
     c = dict(synth.CONFIGS[graph_cfg])
     gen = c.pop("kind")
     scale = 64
@@ -163,7 +186,6 @@ def cpu_baseline(graph_cfg, kind, budget_s):
         t0 = time.perf_counter()
         if kind in ("tip", "tip_u"):
             _, st = oracle.tip(g, 0, return_stats=True)
-            # counting walks the same wedges as peeling without graph updates
             wedges = 2 * st["wedges"]
         else:
             _, st = oracle.wing(g, return_stats=True)
@@ -171,11 +193,78 @@ def cpu_baseline(graph_cfg, kind, budget_s):
         dt = time.perf_counter() - t0
         best = dict(value=wedges / dt if dt > 0 else 0.0, unit="wedges/s", cores=1, kind="oracle",
                     sample=f"{g.name}: {kind} side U by sequential bottom-up peeling, {wedges} wedges in {dt:.2f} s "
-                           f"(workload scaled 1/{scale})", seconds=round(dt, 2))
+                           f"(workload scaled 1/{scale})", seconds=round(dt, 2), **info)
         if dt * 4 > budget_s or scale == 1:
             break
         scale //= 2
+    # the oracle's own full-size runs that wrote the stored results
+    full = []
+    for wl, q in (("cl_5m_1m_100m", "tip_u"), ("cl_1m_200k_20m", "tip_u"), ("cl_1m_200k_20m", "tip_v"),
+                  ("cl_500k_100k_5m", "wing")):
+        rec = golden(wl, q)
+        if rec:
+            w = rec.get("oracle_stats", {}).get("wedges")
+            full.append(dict(workload=wl, quantity=q, oracle_seconds=rec["oracle_seconds"],
+                             count_threads=rec.get("oracle_count_threads", 1), peel_wedges=w))
+    best["full_size_oracle_runs"] = full
     return best
+
+
+def load_graph(graph_cfg, cache_dir, synth):
+    """The seeded graph, from an .npz cache when one is given and present."""
+    if cache_dir:
+        path = os.path.join(cache_dir, f"{graph_cfg}.npz")
+        if os.path.exists(path):
+            z = np.load(path)
+            g = synth.Graph(int(z["n_u"]), int(z["n_v"]), z["row_ptr"], z["col_idx"], str(z["name"]))
+            log(f"[bench] loaded {graph_cfg} from {path}")
+            return g
+    g = synth.config_graph(graph_cfg, log=log)
+    if cache_dir:
+        os.makedirs(cache_dir, exist_ok=True)
+        np.savez(os.path.join(cache_dir, f"{graph_cfg}.npz"), row_ptr=g.row_ptr, col_idx=g.col_idx, n_u=g.n_u,
+                 n_v=g.n_v, name=g.name)
+    return g
+
+
+def side_entry(pb, st, q, res, graph_cfg, ref=None):
+    rec = golden(graph_cfg, q)
+    imb = st["fd_work_max"] / max(st["fd_work_sum"] / max(st["partitions"], 1), 1)
+    d = dict(side=q, ms_total=round(st["ms_total"], 2), ms_cd=round(st["ms_cd"], 2), ms_fd=round(st["ms_fd"], 2),
+             rho=st["rho"], partitions=st["partitions"], fd_imbalance=round(imb, 2), rule_used=st["bound_rule_used"],
+             exact=(digest(pb.to_numpy_u64(res)) == rec["sha256"]) if rec else None)
+    if ref is not None:
+        d["identical_to_plain"] = digest(pb.to_numpy_u64(res)) == ref
+    return d
+
+
+def extra_workload(pb, torch, ctx, name, cache_dir):
+    """One warm and one measured pass of another workload (time and parity)."""
+    import synth
+
+    graph_cfg, kind, P = WORKLOADS[name]
+    g = load_graph(graph_cfg, cache_dir, synth)
+    dg = pb.DeviceGraph.from_graph(g)
+    run_step(pb, ctx, dg, kind, P, 0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs, stats = run_step(pb, ctx, dg, kind, P, 0)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    qn = {"tip": ["tip_u", "tip_v"], "tip_u": ["tip_u"], "wing": ["wing"]}[kind]
+    parity = {}
+    for q, t in zip(qn, outs):
+        rec = golden(graph_cfg, q)
+        parity[q] = (digest(pb.to_numpy_u64(t)) == rec["sha256"]) if rec else None
+    wedges = sum(s["wedges"] for s in stats)
+    d = dict(workload=g.name, ms=round(ms, 2), wedges=wedges, wedges_per_s=round(wedges / (ms / 1e3), 1),
+             phases_ms=[{k: round(s[k], 2) for k in ("ms_total", "ms_count", "ms_cd", "ms_fd_prep", "ms_fd")}
+                        for s in stats],
+             rho=[s["rho"] for s in stats], parity_vs_oracle=parity)
+    if kind == "wing":
+        d.update(updates=stats[0]["updates"], links=stats[0]["links"], blooms=stats[0]["blooms"])
+    del dg
+    return d
 
 
 def main():
@@ -183,10 +272,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="tip_cl_1m_200k_20m", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="tip_u_cl_5m_1m_100m", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-plain bound comparison")
+    ap.add_argument("--no-learned", action="store_true", help="skip the comparison of bound rules")
+    ap.add_argument("--no-extras", action="store_true", help="skip the other workloads' extra keys")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for the CPU baseline")
+    ap.add_argument("--graph-cache", default=None, help="directory for .npz copies of the generated graphs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported",
@@ -208,7 +299,7 @@ def main():
                         name=f"{nb} graphs, m log-uniform in [{m_min:.0e}, {m_max:.0e}], half ER half CL")
         g_m = sum(x.m for x in graphs)
     else:
-        g = synth.config_graph(graph_cfg, log=log)
+        g = load_graph(graph_cfg, args.graph_cache, synth)
         g_m = g.m
     log(f"[bench] graph {g.name}: m={g_m}")
     ctx = pb.Context()
@@ -225,12 +316,13 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] warmup {i + 1}/{args.warmup} done")
 
+    # timed steps: the library's default path (captured coarse-grained rounds)
     step_ms, all_stats, outs = [], [], None
     torch.cuda.synchronize()
     t_all = time.perf_counter()
     for i in range(args.steps):
         t0 = time.perf_counter()
-        outs, stats = run_step(pb, ctx, dg, kind, P, pb.binding.F_KERNEL_TIMING)
+        outs, stats = run_step(pb, ctx, dg, kind, P, 0)
         torch.cuda.synchronize()
         step_ms.append((time.perf_counter() - t0) * 1e3)
         all_stats.append(stats)
@@ -242,14 +334,18 @@ def main():
     value = sum(wedges_per_step) / total_s
     ms_per_step = total_s * 1e3 / args.steps
 
-    # dominant kernel class over the timed steps
+    # kernel-timing pass: HIP events around every kernel class on the
+    # library's stream (coarse-grained tip rounds are host-driven under
+    # timing, since events recorded inside a captured graph cannot be timed;
+    # the kernels and their grids of work are the same)
+    _, tstats = run_step(pb, ctx, dg, kind, P, pb.binding.F_KERNEL_TIMING)
+    torch.cuda.synchronize()
     agg = {}
-    for st in all_stats:
-        for s in st:
-            for name, k in s["kstat"].items():
-                a = agg.setdefault(name, dict(ms=0.0, launches=0, bytes=0, wedges=0))
-                for f in a:
-                    a[f] += k[f]
+    for s in tstats:
+        for name, k in s["kstat"].items():
+            a = agg.setdefault(name, dict(ms=0.0, launches=0, bytes=0, wedges=0))
+            for f in a:
+                a[f] += k[f]
     dom = max(agg, key=lambda n: agg[n]["ms"])
     d = agg[dom]
     achieved = d["bytes"] / (d["ms"] / 1e3) / 1e9 if d["ms"] > 0 else 0.0
@@ -258,7 +354,9 @@ def main():
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=profile_traffic(dom, args.workload),
                     avg_launch_ms=round(d["ms"] / max(d["launches"], 1), 4), launches=d["launches"],
                     algorithmic_bytes=d["bytes"], wedges=d["wedges"],
-                    kernel_wedges_per_s=round(d["wedges"] / (d["ms"] / 1e3), 1) if d["ms"] > 0 else 0.0)
+                    kernel_wedges_per_s=round(d["wedges"] / (d["ms"] / 1e3), 1) if d["ms"] > 0 else 0.0,
+                    timing_pass_ms=round(sum(s["ms_total"] for s in tstats), 2),
+                    classes_ms={n: round(a["ms"], 2) for n, a in agg.items() if a["ms"] > 0})
 
     # parity evidence against stored oracle results (when present)
     parity = {}
@@ -274,28 +372,36 @@ def main():
     work = [{k: s[k] for k in ("wedges", "wedges_count", "wedges_cd", "wedges_fd", "rho", "recounts", "partitions",
                                 "P_used", "fd_work_max", "fd_work_sum", "updates", "links", "blooms")} for s in last]
 
-    # learned vs plain range bounds on the same graph and P, outside the timed
-    # steps (tip workloads, when a trained predictor is stored)
-    learned = None
+    # bound rules on the same graph and P, outside the timed steps (tip
+    # workloads): the library's plain rule, the paper's rule alone, learned
+    rules = None
     if kind in ("tip", "tip_u") and not args.no_learned:
         from paper_2110_12511_amd import predictor
 
-        if predictor.install(ctx):
-            learned = {}
-            for rule_name, rule in (("plain", pb.BOUND_PLAIN), ("learned", pb.BOUND_LEARNED)):
-                per_side = []
-                for side in ((pb.SIDE_U, pb.SIDE_V) if kind == "tip" else (pb.SIDE_U,)):
-                    t = pb.tip(ctx, dg, side, pb.make_opts(P=P, bound_rule=rule))
-                    torch.cuda.synchronize()
-                    st = ctx.stats()
-                    q = "tip_u" if side == pb.SIDE_U else "tip_v"
-                    rec = golden(graph_cfg, q)
-                    imb = st["fd_work_max"] / max(st["fd_work_sum"] / max(st["partitions"], 1), 1)
-                    per_side.append(dict(side=q, ms_total=round(st["ms_total"], 2), ms_cd=round(st["ms_cd"], 2),
-                                         ms_fd=round(st["ms_fd"], 2), rho=st["rho"], partitions=st["partitions"],
-                                         fd_imbalance=round(imb, 2), rule_used=st["bound_rule_used"],
-                                         exact=(digest(pb.to_numpy_u64(t)) == rec["sha256"]) if rec else None))
-                learned[rule_name] = per_side
+        have_pred = predictor.install(ctx)
+        rules = {}
+        ref = {}
+        for rule_name, rule in (("plain", pb.BOUND_PLAIN), ("paper", pb.BOUND_PAPER), ("learned", pb.BOUND_LEARNED)):
+            if rule_name == "learned" and not have_pred:
+                continue
+            per_side = []
+            for side in ((pb.SIDE_U, pb.SIDE_V) if kind == "tip" else (pb.SIDE_U,)):
+                t = pb.tip(ctx, dg, side, pb.make_opts(P=P, bound_rule=rule))
+                torch.cuda.synchronize()
+                q = "tip_u" if side == pb.SIDE_U else "tip_v"
+                if rule_name == "plain":
+                    ref[q] = digest(pb.to_numpy_u64(t))
+                per_side.append(side_entry(pb, ctx.stats(), q, t, graph_cfg, ref.get(q) if rule_name != "plain" else None))
+            rules[rule_name] = per_side
+            log(f"[bench] bound rule {rule_name}: " + ", ".join(f"{e['side']} {e['ms_total']} ms" for e in per_side))
+
+    extras = None
+    if not args.no_extras and args.workload == "tip_u_cl_5m_1m_100m":
+        del outs
+        extras = {}
+        for name in ("tip_cl_1m_200k_20m", "wing_cl_500k_100k_5m"):
+            extras[name] = extra_workload(pb, torch, ctx, name, args.graph_cache)
+            log(f"[bench] extra {name}: {extras[name]['ms']} ms")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -324,7 +430,8 @@ def main():
         "work": work,
         "roofline": roofline,
         "copy_kernel": copy,
-        "learned_vs_plain": learned,
+        "learned_vs_plain": rules,
+        "extras": extras,
         "cpu_baseline": cpu,
         "parity_vs_oracle": parity or None,
     }

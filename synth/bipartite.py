@@ -3,6 +3,7 @@ from __future__ import annotations
 
 import dataclasses
 import hashlib
+import os
 
 import numpy as np
 
@@ -105,6 +106,27 @@ def _capped_weights(n: int, m: int, gamma: float, cap: float) -> np.ndarray:
     return np.minimum(hi * r, cap)
 
 
+def _searchsorted_right(cdf: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """np.searchsorted(cdf, x, side="right"), element by element, on several
+    host threads for large x (numpy releases the interpreter lock inside)."""
+    n = x.shape[0]
+    if n < (1 << 22):
+        return np.searchsorted(cdf, x, side="right")
+    from concurrent.futures import ThreadPoolExecutor
+
+    out = np.empty(n, dtype=np.int64)
+    k = min(16, os.cpu_count() or 1)
+    bounds = np.linspace(0, n, k + 1).astype(np.int64)
+
+    def part(i):
+        a, b = bounds[i], bounds[i + 1]
+        out[a:b] = np.searchsorted(cdf, x[a:b], side="right")
+
+    with ThreadPoolExecutor(k) as ex:
+        list(ex.map(part, range(k)))
+    return out
+
+
 def chung_lu(n_u: int, n_v: int, m: int, gamma: float, cap: float, seed: int, log=None) -> Graph:
     """Chung-Lu bipartite graph with power-law expected degrees on both sides.
     ``log`` (optional) receives a progress line after every draw round."""
@@ -120,8 +142,10 @@ def chung_lu(n_u: int, n_v: int, m: int, gamma: float, cap: float, seed: int, lo
     draws = []
     batch = int(m * 1.25) + 1024
     for _ in range(64):
-        xu = np.searchsorted(cu, rng.random(batch), side="right")
-        xv = np.searchsorted(cv, rng.random(batch), side="right")
+        xu = _searchsorted_right(cu, rng.random(batch))
+        xv = _searchsorted_right(cv, rng.random(batch))
+        if log:
+            log(f"[synth] CL({n_u},{n_v},{m}): {batch} endpoint pairs drawn")
         np.minimum(xu, n_u - 1, out=xu)
         np.minimum(xv, n_v - 1, out=xv)
         draws.append(pu[xu] * n_v + pv[xv])
