@@ -394,6 +394,18 @@ def main():
                 per_side.append(side_entry(pb, ctx.stats(), q, t, graph_cfg, ref.get(q) if rule_name != "plain" else None))
             rules[rule_name] = per_side
             log(f"[bench] bound rule {rule_name}: " + ", ".join(f"{e['side']} {e['ms_total']} ms" for e in per_side))
+        # the learned rule with perfect predictions (the exact tip numbers as
+        # hint): the most any predictor could change the schedule
+        per_side = []
+        for side in ((pb.SIDE_U, pb.SIDE_V) if kind == "tip" else (pb.SIDE_U,)):
+            q = "tip_u" if side == pb.SIDE_U else "tip_v"
+            exact = pb.tip(ctx, dg, side, pb.make_opts(P=P))
+            t = pb.tip_hinted(ctx, dg, side, exact, pb.make_opts(P=P))
+            torch.cuda.synchronize()
+            per_side.append(side_entry(pb, ctx.stats(), q, t, graph_cfg, ref.get(q)))
+            del exact
+        rules["learned_perfect_predictions"] = per_side
+        log("[bench] learned rule, perfect predictions: " + ", ".join(f"{e['side']} {e['ms_total']} ms" for e in per_side))
 
     extras = None
     if not args.no_extras and args.workload == "tip_u_cl_5m_1m_100m":

@@ -214,6 +214,16 @@ int pbng_count_noalloc(pbng_ctx *ctx, const pbng_csr *g, pbng_count_kind kind,
 int pbng_tip(pbng_ctx *ctx, const pbng_csr *g, pbng_side side,
              const pbng_opts *opts, uint64_t *tip_out);
 
+/* Tip numbers with the learned range bounds taken from caller-supplied
+ * predicted tip numbers instead of the predictor (Section 3.1.3 with the
+ * support key replaced by a prediction): theta_hint uint64[n_side], in the
+ * graph's memory space, read only.  Results never depend on the hint; with
+ * the exact tip numbers as hint it shows what a perfect predictor would do
+ * to the schedule.                                                         */
+int pbng_tip_hinted(pbng_ctx *ctx, const pbng_csr *g, pbng_side side,
+                    const pbng_opts *opts, const uint64_t *theta_hint,
+                    uint64_t *tip_out);
+
 /* Tip numbers plus the coarse-grained schedule that produced them (Section
  * 3.1, Algorithm 4; Theorem 1 states what it must satisfy).  Outputs, all in
  * the graph's memory space:

@@ -27,6 +27,7 @@ from .binding import (  # noqa: F401
     tip,
     tip_batch,
     tip_schedule,
+    tip_hinted,
     tip_features,
     wing_batch,
     to_numpy_u64,

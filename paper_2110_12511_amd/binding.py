@@ -118,7 +118,7 @@ class Stats(ctypes.Structure):
 EXPORTS = ["pbng_create", "pbng_destroy", "pbng_last_error", "pbng_last_stats", "pbng_count", "pbng_tip", "pbng_wing",
            "pbng_tip_features", "pbng_mlp_init", "pbng_mlp_set", "pbng_mlp_get", "pbng_mlp_forward",
            "pbng_mlp_loss_grad", "pbng_mlp_train", "pbng_tip_batch", "pbng_wing_batch", "pbng_autotune",
-           "pbng_tip_schedule", "pbng_predictor_load", "pbng_count_noalloc"]
+           "pbng_tip_schedule", "pbng_predictor_load", "pbng_count_noalloc", "pbng_tip_hinted"]
 MLP_NPARAM = 8961
 
 _lib = None
@@ -170,6 +170,7 @@ def load():
         "pbng_tip_schedule": [vp, ctypes.POINTER(Csr), ctypes.c_int, ctypes.POINTER(Opts), vp, vp, vp, vp,
                               ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
         "pbng_predictor_load": [vp, ctypes.c_char_p],
+        "pbng_tip_hinted": [vp, ctypes.POINTER(Csr), ctypes.c_int, ctypes.POINTER(Opts), vp, vp],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -338,6 +339,16 @@ def tip(ctx: Context, dg: DeviceGraph, side: int, opts: Opts | None = None):
     n = dg.n_u if side == SIDE_U else dg.n_v
     out = _out_tensor(n)
     ctx.tip_raw(dg.csr(), side, out.data_ptr(), opts)
+    return out[:n]
+
+
+def tip_hinted(ctx: Context, dg: DeviceGraph, side: int, hint, opts: Opts | None = None):
+    """Tip numbers of one side with learned bounds from predicted tip numbers
+    `hint` (uint64 device tensor of the side's size)."""
+    n = dg.n_u if side == SIDE_U else dg.n_v
+    out = _out_tensor(n)
+    ctx._check(ctx.lib.pbng_tip_hinted(ctx.h, ctypes.byref(dg.csr()), side, ctypes.byref(opts) if opts else None,
+                                       ctypes.c_void_p(hint.data_ptr()), ctypes.c_void_p(out.data_ptr())))
     return out[:n]
 
 

@@ -351,6 +351,44 @@ int pbng_tip(pbng_ctx *x, const pbng_csr *g, pbng_side side, const pbng_opts *op
     });
 }
 
+int pbng_tip_hinted(pbng_ctx *x, const pbng_csr *g, pbng_side side, const pbng_opts *opts, const uint64_t *theta_hint,
+                    uint64_t *tip_out) {
+    if (!x) return PBNG_E_ARG;
+    Ctx &c = x->c;
+    int rc = check_csr(g);
+    if (rc) return fail(c, rc, "bad graph arguments");
+    if (side != PBNG_SIDE_U && side != PBNG_SIDE_V) return fail(c, PBNG_E_ARG, "bad side");
+    const i64 nout = side == PBNG_SIDE_U ? g->n_u : g->n_v;
+    if (nout > 0 && (!tip_out || !theta_hint)) return fail(c, PBNG_E_ARG, "null output or hint");
+    CallScope scope(c);
+    pbng_opts o = default_opts(opts);
+    o.bound_rule = PBNG_BOUND_LEARNED;
+    struct HintReset {
+        Ctx &c;
+        ~HintReset() { c.tip_hint = nullptr; }
+    } reset{c};
+    return guarded(c, [&] {
+        auto t0 = std::chrono::steady_clock::now();
+        c.timing_begin_call((o.flags & PBNG_F_KERNEL_TIMING) != 0);
+        pbng_csr dg = device_graph(c, *g);
+        OutBuf ob(c, tip_out, nout, !g->on_device);
+        u64 *hint = const_cast<u64 *>(theta_hint);
+        if (!g->on_device && nout > 0) {
+            hint = c.alloc<u64>(nout);
+            PBNG_HIP(hipMemcpyAsync(hint, theta_hint, sizeof(u64) * nout, hipMemcpyHostToDevice, c.stream));
+        }
+        c.tip_hint = hint;
+        DevGraph G;
+        build_graph(c, dg, G);
+        PBNG_HIP(hipStreamSynchronize(c.stream));
+        c.stats.ms_prep = ms_since(t0);
+        tip_decompose(c, G, side, o, ob.dev);
+        ob.finish();
+        if (o.flags & PBNG_F_KERNEL_TIMING) c.timing_end_call();
+        c.stats.ms_total = ms_since(t0);
+    });
+}
+
 int pbng_tip_schedule(pbng_ctx *x, const pbng_csr *g, pbng_side side, const pbng_opts *opts, uint64_t *tip_out,
                       int32_t *part_out, uint64_t *init_out, uint64_t *bounds_out, int32_t bounds_cap, int32_t *nparts) {
     if (!x) return PBNG_E_ARG;

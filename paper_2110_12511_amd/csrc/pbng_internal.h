@@ -88,6 +88,8 @@ struct Ctx {
     // stream used only to capture round graphs (replayed on `stream`)
     hipStream_t cap_stream = nullptr;
     hipStream_t capture_stream();
+    // predicted tip numbers supplied for one call (pbng_tip_hinted, device)
+    const u64 *tip_hint = nullptr;
     // device address of the library's static scratch array on this
     // context's device (pbng_count_noalloc)
     void *scratch = nullptr;

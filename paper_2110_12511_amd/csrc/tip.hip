@@ -1594,9 +1594,12 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
     double *one_dev = nullptr;
     c.stats.bound_rule_used = (o.bound_rule == PBNG_BOUND_RANDOM || o.bound_rule == PBNG_BOUND_PAPER) ? o.bound_rule
                                                                                                  : PBNG_BOUND_PLAIN;
-    if (o.bound_rule == PBNG_BOUND_LEARNED && c.mlp_ready) {
+    if (o.bound_rule == PBNG_BOUND_LEARNED && (c.mlp_ready || c.tip_hint)) {
         that = c.alloc<u64>(nx);
-        learned_theta_hat(c, G, side, sup, that);
+        if (c.tip_hint)  // predictions supplied by the caller
+            PBNG_HIP(hipMemcpyAsync(that, c.tip_hint, sizeof(u64) * nx, hipMemcpyDeviceToDevice, s));
+        else
+            learned_theta_hat(c, G, side, sup, that);
         one_dev = c.alloc<double>(1);
         const double one = 1.0;
         PBNG_HIP(hipMemcpyAsync(one_dev, &one, sizeof(double), hipMemcpyHostToDevice, s));

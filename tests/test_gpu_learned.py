@@ -128,6 +128,33 @@ def test_learned_without_predictor_falls_back(cl_mid):
     c2.close()
 
 
+@pytest.mark.parametrize("P", [7, 150])
+def test_hinted_bounds_exact(ctx, cl_mid, P):
+    """Learned bounds from supplied predictions: results never depend on
+    them (exact, zero, support-sized and random hints).  The fine-grained
+    imbalance under perfect predictions (the exact tip numbers) is printed
+    beside the plain rule's: it is not always lower, since the bound's work
+    weights are taken at partition start while the fine-grained work counts
+    only wedges inside the partition."""
+    g, eu, _ = cl_mid
+    dg = pb.DeviceGraph.from_graph(g)
+    S = oracle.count_vertex(g)[0]
+    rng = np.random.default_rng(P)
+    imb = {}
+    for name, hint in (("exact", eu), ("zero", np.zeros_like(eu)), ("support", S),
+                       ("random", rng.integers(0, int(S.max()) + 1, size=S.size).astype(np.uint64))):
+        h = torch.as_tensor(hint.astype(np.int64)).cuda().view(torch.uint64)
+        got = u64(pb.tip_hinted(ctx, dg, 0, h, pb.make_opts(P=P)))
+        assert np.array_equal(got, eu), name
+        st = ctx.stats()
+        assert st["bound_rule_used"] == pb.BOUND_LEARNED
+        imb[name] = st["fd_work_max"] / max(st["fd_work_sum"] / max(st["partitions"], 1), 1)
+    pb.tip(ctx, dg, 0, pb.make_opts(P=P))
+    st = ctx.stats()
+    plain = st["fd_work_max"] / max(st["fd_work_sum"] / max(st["partitions"], 1), 1)
+    print(f"P={P}: fine-grained imbalance plain {plain:.2f}, perfect predictions {imb['exact']:.2f}")
+
+
 def test_stored_predictor_gain(ctx):
     """What the stored network (trained on 2000 seeded graphs) gains: on a
     held-out graph its predicted ratios theta / support are much closer to
