@@ -56,52 +56,130 @@ __global__ void m_densify(const i32 *hubs, const u32 *nh, const i64 *xrow, const
     }
 }
 
-// Gram tiles: a 256-lane workgroup owns a 64 x 64 output tile; wave w owns
-// rows 16w..16w+15 of it as four 16 x 16 accumulators.  v_mfma 16x16x64 i8:
-// lane l feeds row (l % 16) with bytes k0 + 16 (l / 16) .. +15 of A, and the
-// same bytes of column (l % 16) of B; accumulator entry i of lane l is row
-// 4 (l / 16) + i, column l % 16.  B = A_H^T, so both operands are hub rows.
-// Each output row sums C(c, 2) over the other hubs and adds it to its hub.
+// Gram tiles.  The Gram matrix is symmetric, so only tiles (bi, bj) with
+// bi <= bj of the 128 x 128 tiling are computed, and each count c(x, x')
+// credits C(c, 2) to both hubs (on a diagonal tile, only entries above the
+// diagonal).  A 256-lane workgroup owns one tile: per step it stages 128
+// rows x 128 bytes of each operand in LDS (rows padded by 16 bytes against
+// bank conflicts), loading the next step into registers while the matrix
+// cores work on the current one, and wave w computes the 64 x 64 quarter
+// (w / 2, w % 2) as 4 x 4 v_mfma_i32_16x16x64_i8 tiles.  v_mfma 16x16x64 i8:
+// lane l feeds row (l % 16) with bytes 16 (l / 16) .. +15 of the 64-byte k
+// chunk of A, and the same bytes of column (l % 16) of B; accumulator entry
+// e of lane l is row 4 (l / 16) + e, column l % 16.  B = A_H^T, so both
+// operands are hub rows.
+constexpr int GT = 128;        // output tile
+constexpr int GK = 128;        // k bytes per step (two 64-byte MFMA chunks)
+constexpr int GROW = GK + 16;  // padded LDS row
+
+__device__ __forceinline__ void gram_tile_of(u32 t, u32 nt, u32 &bi, u32 &bj) {
+    // t-th pair (bi, bj), bi <= bj, in row-major order of the upper triangle
+    u32 r = 0, rem = t;
+    while (rem >= nt - r) {
+        rem -= nt - r;
+        ++r;
+    }
+    bi = r;
+    bj = r + rem;
+}
+
 __global__ __launch_bounds__(256) void m_gram(const signed char *D, i64 kp, u32 h, const i32 *hubs, u64 *out,
                                              KCounters *kc) {
+    __shared__ __attribute__((aligned(16))) signed char sA[GT * GROW];
+    __shared__ __attribute__((aligned(16))) signed char sB[GT * GROW];
     const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
-    const i64 r0 = (i64)blockIdx.y * 64 + 16 * w;
-    const i64 c0 = (i64)blockIdx.x * 64;
-    const i64 arow = r0 + (lane & 15);
-    const int kq = (lane >> 4) * 16;
-    v4i acc[4];
-    for (int b = 0; b < 4; ++b) acc[b] = (v4i){0, 0, 0, 0};
+    const u32 nt = (h + GT - 1) / GT;
+    u32 bi, bj;
+    gram_tile_of(blockIdx.x, nt, bi, bj);
+    const i64 ra0 = (i64)bi * GT, rb0 = (i64)bj * GT;
+    // staging: thread t loads 16-byte pieces (row t / 8 + 32 q, bytes 16 (t % 8))
+    const int lr = threadIdx.x >> 3, lc = (threadIdx.x & 7) * 16;
     const v4i zero = {0, 0, 0, 0};
-    for (i64 k0 = 0; k0 < kp; k0 += 64) {
-        const v4i a = arow < h ? *reinterpret_cast<const v4i *>(D + arow * kp + k0 + kq) : zero;
-        for (int b = 0; b < 4; ++b) {
-            const i64 bcol = c0 + 16 * b + (lane & 15);
-            const v4i bv = bcol < h ? *reinterpret_cast<const v4i *>(D + bcol * kp + k0 + kq) : zero;
-            acc[b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, bv, acc[b], 0, 0, 0);
+    v4i pa[4], pb[4];
+    auto load = [&](i64 k0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const i64 ra = ra0 + lr + 32 * q, rb = rb0 + lr + 32 * q;
+            pa[q] = ra < h ? *reinterpret_cast<const v4i *>(D + ra * kp + k0 + lc) : zero;
+            pb[q] = rb < h ? *reinterpret_cast<const v4i *>(D + rb * kp + k0 + lc) : zero;
+        }
+    };
+    const int wr = (w >> 1) * 64, wc = (w & 1) * 64;
+    v4i acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = zero;
+    load(0);
+    for (i64 k0 = 0; k0 < kp; k0 += GK) {
+        __syncthreads();  // the previous step's reads of the LDS tiles are done
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            *reinterpret_cast<v4i *>(sA + (lr + 32 * q) * GROW + lc) = pa[q];
+            *reinterpret_cast<v4i *>(sB + (lr + 32 * q) * GROW + lc) = pb[q];
+        }
+        __syncthreads();
+        if (k0 + GK < kp) load(k0 + GK);
+#pragma unroll
+        for (int kc = 0; kc < GK; kc += 64) {
+            v4i a[4], b[4];
+            const int off = kc + 16 * (lane >> 4);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                a[i] = *reinterpret_cast<const v4i *>(sA + (wr + 16 * i + (lane & 15)) * GROW + off);
+                b[i] = *reinterpret_cast<const v4i *>(sB + (wc + 16 * i + (lane & 15)) * GROW + off);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[i], b[j], acc[i][j], 0, 0, 0);
         }
     }
-    u64 rs[4] = {0, 0, 0, 0};
-    for (int b = 0; b < 4; ++b) {
-        const i64 col = c0 + 16 * b + (lane & 15);
-        for (int i = 0; i < 4; ++i) {
-            const i64 row = r0 + 4 * (lane >> 4) + i;
-            if (row < h && col < h && row != col) {
-                const u64 cc = (u64)(u32)acc[b][i];
-                rs[i] += cc * (cc - 1) / 2;
+    // C(c, 2) of every counted pair to both hubs: row sums over the lanes of
+    // a row group, column sums over the lanes of a column
+    u64 rs[4][4], cs[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) cs[j] = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) rs[i][e] = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const i64 gc = rb0 + wc + 16 * j + (lane & 15);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const i64 gr = ra0 + wr + 16 * i + 4 * (lane >> 4) + e;
+                if (gr < h && gc < h && (bi < bj || gr < gc)) {
+                    const u64 cc = (u64)(u32)acc[i][j][e];
+                    const u64 v = cc * (cc - 1) / 2;
+                    rs[i][e] += v;
+                    cs[j] += v;
+                }
             }
         }
     }
-    // rows are shared by the 16 lanes with the same lane / 16
-    for (int i = 0; i < 4; ++i) {
-        u64 v = rs[i];
-        for (int d = 1; d < 16; d <<= 1) v += __shfl_xor(v, d, WAVE);
-        const i64 row = r0 + 4 * (lane >> 4) + i;
-        if ((lane & 15) == 0 && row < h && v) atomicAdd((unsigned long long *)&out[hubs[row]], (unsigned long long)v);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            u64 v = rs[i][e];
+            for (int d = 1; d < 16; d <<= 1) v += __shfl_xor(v, d, WAVE);
+            const i64 gr = ra0 + wr + 16 * i + 4 * (lane >> 4) + e;
+            if ((lane & 15) == 0 && gr < h && v) atomicAdd((unsigned long long *)&out[hubs[gr]], (unsigned long long)v);
+        }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        u64 v = cs[j];
+        v += __shfl_xor(v, 16, WAVE);
+        v += __shfl_xor(v, 32, WAVE);
+        const i64 gc = rb0 + wc + 16 * j + (lane & 15);
+        if (lane < 16 && gc < h && v) atomicAdd((unsigned long long *)&out[hubs[gc]], (unsigned long long)v);
     }
-    // multiply-adds issued (2 ops each) and the tile bytes read
+    // multiply-adds issued (2 ops each) and the operand bytes read
     if (threadIdx.x == 0) {
-        atomicAdd((unsigned long long *)&kc->wedges, (unsigned long long)(2ull * 64 * 64 * (u64)kp));
-        atomicAdd((unsigned long long *)&kc->items, (unsigned long long)(2ull * 64 * (u64)kp));
+        atomicAdd((unsigned long long *)&kc->wedges, (unsigned long long)(2ull * GT * GT * (u64)kp));
+        atomicAdd((unsigned long long *)&kc->items, (unsigned long long)(2ull * GT * (u64)kp));
     }
 }
 
@@ -132,15 +210,16 @@ u64 count_side(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 *out
     const u64 w = count_pass_xside(c, G, sl, lclass);
     gather_side(c, G, sl, side, out);
     if (h >= 2) {
-        const i64 kp = (ny + 63) / 64 * 64;
+        const i64 kp = (ny + GK - 1) / GK * GK;
         signed char *D = c.alloc<signed char>((i64)h * kp);
         PBNG_HIP(hipMemsetAsync(D, 0, (size_t)h * kp, s));
         hipLaunchKernelGGL(m_densify, dim3(grid_1d((i64)h * WAVE)), dim3(256), 0, s, (const i32 *)hubs, (const u32 *)nh, xrow,
                            xadj, kp, D);
         PBNG_LAUNCH_CHECK();
-        const u32 tiles = (h + 63) / 64;
+        const u32 nt = (h + GT - 1) / GT;
+        const u32 tiles = nt * (nt + 1) / 2;  // upper triangle
         c.kbegin(PBNG_K_DENSE);
-        hipLaunchKernelGGL(m_gram, dim3(tiles, tiles), dim3(256), 0, s, (const signed char *)D, kp, h, (const i32 *)hubs, out,
+        hipLaunchKernelGGL(m_gram, dim3(tiles), dim3(256), 0, s, (const signed char *)D, kp, h, (const i32 *)hubs, out,
                            c.kctr + PBNG_K_DENSE);
         c.kend(PBNG_K_DENSE);
         PBNG_LAUNCH_CHECK();
