@@ -139,7 +139,7 @@ typedef struct {
                            (the larger of 2^16 and 4096 per 2^16-vertex tile
                            of the side), negative = never (schedule only)    */
     int32_t batch_edges;/* batch calls: most edges packed into one union
-                           graph; 0 = library default (2^28)                 */
+                           graph; 0 = library default (2^26)                 */
     int32_t wide_work;  /* wing: fine-grained work above which a partition
                            is peeled by device-wide kernels; 0 = library
                            default (2^24), negative = never (schedule only)  */

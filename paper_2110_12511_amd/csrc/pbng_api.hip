@@ -509,7 +509,9 @@ int batch_call(pbng_ctx *x, const pbng_csr *g, int32_t ng, int kind, int side, c
     }
     CallScope scope(c);
     pbng_opts o = default_opts(opts);
-    const i64 max_m = o.batch_edges > 0 ? (i64)o.batch_edges : (i64(1) << 28);
+    // per-workgroup scratch of the largest starts and of spilled hash keys
+    // scales with the union's vertex count, so unions stay moderate
+    const i64 max_m = o.batch_edges > 0 ? (i64)o.batch_edges : (i64(1) << 26);
     return guarded(c, [&] {
         auto t0 = std::chrono::steady_clock::now();
         c.timing_begin_call((o.flags & PBNG_F_KERNEL_TIMING) != 0);

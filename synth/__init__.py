@@ -36,6 +36,8 @@ from .bipartite import (  # noqa: F401
     disjoint_union,
     random_small,
     mixed_graph,
+    mixed_graphs,
+    mixed_edges,
     config_graph,
     CONFIGS,
 )

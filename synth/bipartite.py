@@ -198,6 +198,52 @@ CONFIGS = {
 }
 
 
+def _mixed_args(gi: int, m_min: float, m_max: float):
+    rng = np.random.default_rng(50000 + gi)
+    m = int(round(np.exp(rng.uniform(np.log(m_min), np.log(m_max)))))
+    if gi % 2 == 0:
+        return ("er", max(m // 10, 2), max(m // 20, 2), m, 0.0)
+    return ("cl", max(m // 10, 2), max(m // 50, 2), m, float(rng.uniform(2.0, 2.6)))
+
+
+def mixed_graph(gi: int, m_min: float = 1e3, m_max: float = 1e6) -> Graph:
+    """Graph gi of a family of uneven sizes for batched calls: m log-uniform in
+    [m_min, m_max]; even gi Erdos-Renyi with |U| = m/10, |V| = m/20; odd gi
+    Chung-Lu with exponent uniform in [2.0, 2.6], |U| = m/10, |V| = m/50,
+    degree cap 50000.  Seeds 50000 + gi."""
+    kind, n_u, n_v, m, gamma = _mixed_args(gi, m_min, m_max)
+    if kind == "er":
+        return er(n_u, n_v, m, seed=50000 + gi)
+    return chung_lu(n_u, n_v, m, gamma, 50000, seed=50000 + gi)
+
+
+def mixed_edges(gi: int, m_min: float = 1e3, m_max: float = 1e6) -> int:
+    """Edge count of mixed_graph(gi) without drawing the graph."""
+    return _mixed_args(gi, m_min, m_max)[3]
+
+
+def _mixed_worker(args):
+    g = mixed_graph(*args)
+    return g.n_u, g.n_v, g.row_ptr, g.col_idx, g.name
+
+
+def mixed_graphs(indices, m_min: float = 1e3, m_max: float = 1e6, workers: int = 0):
+    """mixed_graph(gi) for every gi of indices, drawn by a pool of host
+    processes (workers = 0: one per core, at most 16); same graphs as one
+    at a time."""
+    indices = list(indices)
+    k = workers or min(16, os.cpu_count() or 1)
+    if k <= 1 or len(indices) < 8:
+        return [mixed_graph(i, m_min, m_max) for i in indices]
+    from concurrent.futures import ProcessPoolExecutor
+    import multiprocessing as mp
+
+    # fresh interpreters: the caller may hold GPU state that a fork would copy
+    with ProcessPoolExecutor(k, mp_context=mp.get_context("spawn")) as ex:
+        out = list(ex.map(_mixed_worker, [(i, m_min, m_max) for i in indices], chunksize=4))
+    return [Graph(n_u, n_v, rp, ci, name) for n_u, n_v, rp, ci, name in out]
+
+
 def config_graph(name: str, log=None) -> Graph:
     c = dict(CONFIGS[name])
     kind = c.pop("kind")
@@ -206,13 +252,3 @@ def config_graph(name: str, log=None) -> Graph:
     return chung_lu(**c, log=log)
 
 
-def mixed_graph(gi: int, m_min: float = 1e3, m_max: float = 1e6) -> Graph:
-    """Graph gi of a family of uneven sizes for batched calls: m log-uniform in
-    [m_min, m_max]; even gi Erdos-Renyi with |U| = m/10, |V| = m/20; odd gi
-    Chung-Lu with exponent uniform in [2.0, 2.6], |U| = m/10, |V| = m/50,
-    degree cap 50000.  Seeds 50000 + gi."""
-    rng = np.random.default_rng(50000 + gi)
-    m = int(round(np.exp(rng.uniform(np.log(m_min), np.log(m_max)))))
-    if gi % 2 == 0:
-        return er(max(m // 10, 2), max(m // 20, 2), m, seed=50000 + gi)
-    return chung_lu(max(m // 10, 2), max(m // 50, 2), m, float(rng.uniform(2.0, 2.6)), 50000, seed=50000 + gi)

@@ -10,7 +10,7 @@ import oracle
 import paper_2110_12511_amd as pb
 from paper_2110_12511_amd import binding
 import synth
-from gpu_util import u64
+from gpu_util import u64, digest
 
 pytestmark = pytest.mark.gpu
 
@@ -129,3 +129,38 @@ def test_uneven_batch_matches_single_calls(ctx):
     wres = pb.wing_batch(ctx, [dgs[k] for k in small])
     for k, r in zip(small, wres):
         assert np.array_equal(u64(r), oracle.wing(gs[k])), k
+
+
+def test_batch_4096_graphs_against_oracle(ctx):
+    """The 4096-graph batch (edge counts log-uniform in 1e3 .. 1e6, half
+    Erdos-Renyi, half Chung-Lu): tip numbers of side U of every graph and
+    wing numbers of every graph the stored oracle results cover (all graphs
+    up to 3e5 edges and a seeded sample of larger ones), one batched call
+    each under learned bounds, against the oracle's SHA-256 prefixes."""
+    import json
+    import os
+
+    from paper_2110_12511_amd import predictor
+
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "mixed_4096__batch.json")
+    if not os.path.exists(path):
+        pytest.skip("no stored oracle results for the 4096-graph batch")
+    rec = json.load(open(path))
+    ent = rec["entries"]
+    gs = synth.mixed_graphs(range(rec["n_graphs"]), 1e3, 1e6)
+    for i, g in enumerate(gs):
+        assert g.digest()[:16] == ent[str(i)]["graph"], i
+    rule = pb.BOUND_LEARNED if predictor.install(ctx) else pb.BOUND_PLAIN
+    dgs = [pb.DeviceGraph.from_graph(g) for g in gs]
+    del gs
+    res = pb.tip_batch(ctx, dgs, 0, pb.make_opts(bound_rule=rule))
+    for i, r in enumerate(res):
+        assert digest(u64(r))[:16] == ent[str(i)]["tip_u"], i
+    del res
+    res = pb.wing_batch(ctx, dgs, pb.make_opts(bound_rule=rule))
+    checked = 0
+    for i, r in enumerate(res):
+        if "wing" in ent[str(i)]:
+            checked += 1
+            assert digest(u64(r))[:16] == ent[str(i)]["wing"], i
+    assert checked == rec["wing_covered"]
