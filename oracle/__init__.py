@@ -58,6 +58,10 @@ def _load():
     lib.orc_tip.argtypes = [i64, i64, _i64p, _i32p, i32, _u64p, _u64p, ctypes.c_uint64, ctypes.c_void_p]
     lib.orc_wing.argtypes = [i64, i64, _i64p, _i32p, _u64p, _u64p, ctypes.c_uint64, ctypes.c_void_p]
     lib.orc_set_threads.argtypes = [i32]
+    lib.orc_tip_components.argtypes = [i64, i64, _i64p, _i32p, i32, _u64p, ctypes.c_uint64, _i64p]
+    lib.orc_wing_components.argtypes = [i64, i64, _i64p, _i32p, _u64p, ctypes.c_uint64, _i64p]
+    lib.orc_tip_components.restype = i32
+    lib.orc_wing_components.restype = i32
     for f in (lib.orc_validate, lib.orc_count_vertex, lib.orc_count_edge, lib.orc_tip, lib.orc_wing, lib.orc_set_threads):
         f.restype = i32
     _lib = lib
@@ -141,3 +145,27 @@ def wing(g, return_stats: bool = False, wedge_budget: int = 0, return_order: boo
     if return_order:
         out.append(order)
     return out[0] if len(out) == 1 else tuple(out)
+
+
+def tip_components(g, side: int, theta, k: int):
+    """k-tips of one side (Definition 2): for every vertex with tip number >= k
+    the smallest vertex id of its butterfly-connected component, -1 below k."""
+    n_u, n_v, rp, ci = _csr(g)
+    th = np.ascontiguousarray(theta, dtype=np.uint64)
+    out = np.zeros(max(n_u if side == 0 else n_v, 1), dtype=np.int64)
+    rc = _load().orc_tip_components(n_u, n_v, rp, ci, int(side), th, int(k), out)
+    if rc:
+        raise OracleError(rc, "tip_components")
+    return out[: (n_u if side == 0 else n_v)]
+
+
+def wing_components(g, theta, k: int):
+    """k-wings (Definition 1): for every edge with wing number >= k the
+    smallest edge id of its butterfly-connected component, -1 below k."""
+    n_u, n_v, rp, ci = _csr(g)
+    th = np.ascontiguousarray(theta, dtype=np.uint64)
+    out = np.zeros(max(g.m, 1), dtype=np.int64)
+    rc = _load().orc_wing_components(n_u, n_v, rp, ci, th, int(k), out)
+    if rc:
+        raise OracleError(rc, "wing_components")
+    return out[: g.m]

@@ -113,3 +113,81 @@ def wing(g):
             if k > theta[e]:
                 theta[e] = k
     return theta
+
+
+def _connected(items, links):
+    """True when items (a set) form one component under links (pairs)."""
+    items = set(items)
+    if len(items) <= 1:
+        return True
+    adj = {x: set() for x in items}
+    for a, b in links:
+        if a in items and b in items:
+            adj[a].add(b)
+            adj[b].add(a)
+    start = next(iter(items))
+    seen, stack = {start}, [start]
+    while stack:
+        x = stack.pop()
+        for y in adj[x] - seen:
+            seen.add(y)
+            stack.append(y)
+    return seen == items
+
+
+def _maximal_labels(n, good_sets):
+    """Label each element with the smallest id of the maximal good set that
+    holds it (-1 if none); the maximal sets must be disjoint."""
+    maximal = [s for s in good_sets if not any(s < t for t in good_sets)]
+    lab = np.full(n, -1, np.int64)
+    for s in maximal:
+        for x in s:
+            assert lab[x] == -1, "maximal k-sets overlap"
+            lab[x] = min(s)
+    return lab
+
+
+def tip_components(g, side: int, k: int):
+    """k-tips by Definition 2 read literally: the maximal sets S of the side's
+    vertices (with all of the other side) in which every vertex has at least k
+    butterflies of G[S u other side] and any two are joined by a chain of
+    butterflies; each vertex gets the smallest id of its k-tip, -1 if none."""
+    n = g.n_u if side == 0 else g.n_v
+    if n > 14:
+        raise ValueError("brute-force k-tips are limited to 14 vertices")
+    pairs = [(u, up) if side == 0 else (v, vp) for u, up, v, vp in butterflies(g)]
+    good = []
+    for mask in range(1, 1 << n):
+        members = {x for x in range(n) if (mask >> x) & 1}
+        inside = [(a, b) for a, b in pairs if a in members and b in members]
+        sup = {x: 0 for x in members}
+        for a, b in inside:
+            sup[a] += 1
+            sup[b] += 1
+        if min(sup.values()) >= k and _connected(members, inside):
+            good.append(frozenset(members))
+    return _maximal_labels(n, good)
+
+
+def wing_components(g, k: int):
+    """k-wings by Definition 1 read literally: the maximal edge sets F in
+    which every edge lies in at least k butterflies whose four edges are in F
+    and any two edges are joined by a chain of such butterflies; each edge
+    gets the smallest id of its k-wing, -1 if none."""
+    m = g.m
+    if m > 16:
+        raise ValueError("brute-force k-wings are limited to 16 edges")
+    quads = _butterfly_edges(g)
+    good = []
+    for mask in range(1, 1 << m):
+        members = {e for e in range(m) if (mask >> e) & 1}
+        inside = [q for q in quads if all(e in members for e in q)]
+        sup = {e: 0 for e in members}
+        links = []
+        for q in inside:
+            for e in q:
+                sup[e] += 1
+            links += [(q[0], q[1]), (q[0], q[2]), (q[0], q[3])]
+        if min(sup.values()) >= k and _connected(members, links):
+            good.append(frozenset(members))
+    return _maximal_labels(m, good)

@@ -470,3 +470,119 @@ out:
     free(vptr); free(vadj); free(veid);
     return rc;
 }
+
+/* ---------------------------------------------------------------------- */
+/* k-tips and k-wings from entity numbers (Section 2.2, Definitions 1-2).   */
+/*                                                                          */
+/* The k-tips of side U are the butterfly-connected components of the U     */
+/* vertices with tip number >= k (with all of V): two such vertices are     */
+/* joined when they share at least two neighbours (they lie in a common     */
+/* butterfly).  The k-wings are the butterfly-connected components of the   */
+/* edges with wing number >= k: two edges are joined when some butterfly of */
+/* that edge set holds both.  Components are named by their smallest        */
+/* member id; entities below k get -1.  Union-find with union by smaller    */
+/* root, so every root is its component's smallest id.                      */
+/* ---------------------------------------------------------------------- */
+
+static i64 uf_find(i64 *p, i64 x)
+{
+    while (p[x] != x) x = p[x];
+    return x;
+}
+
+static void uf_union(i64 *p, i64 a, i64 b)
+{
+    a = uf_find(p, a);
+    b = uf_find(p, b);
+    if (a == b) return;
+    if (a < b) p[b] = a; else p[a] = b;
+}
+
+/* side 0: components of U vertices, side 1: of V vertices.                 */
+int orc_tip_components(i64 n_u, i64 n_v, const i64 *row_ptr, const i32 *col, int side,
+                       const u64 *theta, u64 k, i64 *comp)
+{
+    int rc = orc_validate(n_u, n_v, row_ptr, col);
+    if (rc) return rc;
+    if (side != 0 && side != 1) return -1;
+    i64 *vptr; i32 *vadj; i64 *veid;
+    rc = transpose(n_u, n_v, row_ptr, col, &vptr, &vadj, &veid);
+    if (rc) return rc;
+    i64 n_l = side == 0 ? n_u : n_v;
+    const i64 *lptr = side == 0 ? row_ptr : vptr;
+    const i32 *ladj = side == 0 ? col : vadj;
+    const i64 *rptr = side == 0 ? vptr : row_ptr;
+    const i32 *radj = side == 0 ? vadj : col;
+    i64 *p = malloc((size_t)(n_l ? n_l : 1) * sizeof(i64));
+    u64 *cnt = calloc((size_t)(n_l ? n_l : 1), sizeof(u64));
+    i64 *touched = malloc((size_t)(n_l ? n_l : 1) * sizeof(i64));
+    if (!p || !cnt || !touched) { rc = -3; goto out; }
+    for (i64 u = 0; u < n_l; ++u) p[u] = u;
+    for (i64 u = 0; u < n_l; ++u) {
+        if (theta[u] < k) continue;
+        i64 nt = 0;
+        for (i64 j = lptr[u]; j < lptr[u + 1]; ++j) {
+            i32 v = ladj[j];
+            for (i64 q = rptr[v]; q < rptr[v + 1]; ++q) {
+                i32 w = radj[q];
+                if (w == u || theta[w] < k) continue;
+                if (cnt[w] == 0) touched[nt++] = w;
+                cnt[w]++;
+            }
+        }
+        for (i64 t = 0; t < nt; ++t) {
+            i64 w = touched[t];
+            if (cnt[w] >= 2) uf_union(p, u, w);
+            cnt[w] = 0;
+        }
+    }
+    for (i64 u = 0; u < n_l; ++u) comp[u] = theta[u] >= k ? uf_find(p, u) : -1;
+out:
+    free(p); free(cnt); free(touched);
+    free(vptr); free(vadj); free(veid);
+    return rc;
+}
+
+int orc_wing_components(i64 n_u, i64 n_v, const i64 *row_ptr, const i32 *col, const u64 *theta, u64 k,
+                        i64 *comp)
+{
+    int rc = orc_validate(n_u, n_v, row_ptr, col);
+    if (rc) return rc;
+    i64 m = row_ptr[n_u];
+    i64 *vptr; i32 *vadj; i64 *veid;
+    rc = transpose(n_u, n_v, row_ptr, col, &vptr, &vadj, &veid);
+    if (rc) return rc;
+    i64 *p = malloc((size_t)(m ? m : 1) * sizeof(i64));
+    i64 *mark = malloc((size_t)(n_v ? n_v : 1) * sizeof(i64));  /* edge id of (u, v) or -1 */
+    if (!p || !mark) { rc = -3; goto out; }
+    for (i64 e = 0; e < m; ++e) p[e] = e;
+    for (i64 v = 0; v < n_v; ++v) mark[v] = -1;
+    /* every butterfly {(u,v),(u,v'),(u',v),(u',v')} of the edges with wing
+       number >= k, found from its smaller U vertex u, joins its four edges */
+    for (i64 u = 0; u < n_u; ++u) {
+        for (i64 e = row_ptr[u]; e < row_ptr[u + 1]; ++e)
+            if (theta[e] >= k) mark[col[e]] = e;
+        for (i64 e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+            if (theta[e] < k) continue;
+            i32 v = col[e];
+            for (i64 q = vptr[v]; q < vptr[v + 1]; ++q) {
+                i32 w = vadj[q];                 /* u' */
+                i64 f = veid[q];                 /* (u', v) */
+                if (w <= u || theta[f] < k) continue;
+                for (i64 g2 = row_ptr[w]; g2 < row_ptr[w + 1]; ++g2) {
+                    i32 v2 = col[g2];            /* v' */
+                    if (v2 <= v || theta[g2] < k || mark[v2] < 0) continue;
+                    uf_union(p, e, f);
+                    uf_union(p, e, mark[v2]);
+                    uf_union(p, e, g2);
+                }
+            }
+        }
+        for (i64 e = row_ptr[u]; e < row_ptr[u + 1]; ++e) mark[col[e]] = -1;
+    }
+    for (i64 e = 0; e < m; ++e) comp[e] = theta[e] >= k ? uf_find(p, e) : -1;
+out:
+    free(p); free(mark);
+    free(vptr); free(vadj); free(veid);
+    return rc;
+}

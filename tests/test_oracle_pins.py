@@ -286,3 +286,73 @@ def test_single_level_ranges_give_their_level():
                     alive &= ~low
                     s = supports()
             assert np.array_equal(theta, oracle.tip(g, side)), (g.name, side)
+
+
+# ---------------------------------------------------------------- k-tips / k-wings
+
+def test_components_match_definitions_on_tiny_graphs():
+    """The oracle's k-tips and k-wings (components of the entities at level
+    >= k) equal the maximal sets of Definitions 1-2 found by exhaustive
+    search, at every level k of every tiny graph."""
+    for s in range(24):
+        rng = np.random.default_rng(900 + s)
+        g = synth.random_small(int(rng.integers(2, 8)), int(rng.integers(2, 7)), float(rng.choice([0.5, 0.8])),
+                               seed=900 + s)
+        for side in (0, 1):
+            th = oracle.tip(g, side)
+            for k in sorted(set([0] + th.tolist() + [int(th.max()) + 1])):
+                assert np.array_equal(oracle.tip_components(g, side, th, k), brute.tip_components(g, side, k)), \
+                    (g.name, side, k)
+        if g.m <= 13:
+            th = oracle.wing(g)
+            for k in sorted(set([0] + th.tolist() + [int(th.max()) + 1])):
+                assert np.array_equal(oracle.wing_components(g, th, k), brute.wing_components(g, k)), (g.name, k)
+
+
+def test_components_two_squares_sharing_a_vertex():
+    """Squares u0,u1 x v0,v1 and u1,u2 x v2,v3: every entity number is 1.
+    The three U vertices form one 1-tip (u1 shares two neighbours with each
+    of the others), but the edges form two 1-wings: no butterfly holds edges
+    of both squares, although they share the vertex u1."""
+    g = synth.from_edges(3, 4, [(0, 0), (0, 1), (1, 0), (1, 1), (1, 2), (1, 3), (2, 2), (2, 3)])
+    tu = oracle.tip(g, 0)
+    assert tu.tolist() == [1, 1, 1]
+    assert oracle.tip_components(g, 0, tu, 1).tolist() == [0, 0, 0]
+    assert oracle.tip_components(g, 0, tu, 2).tolist() == [-1, -1, -1]
+    tw = oracle.wing(g)
+    assert tw.tolist() == [1] * 8
+    assert oracle.wing_components(g, tw, 1).tolist() == [0, 0, 0, 0, 4, 4, 4, 4]
+    assert oracle.wing_components(g, tw, 2).tolist() == [-1] * 8
+    tv = oracle.tip(g, 1)
+    # V side: v0, v1 share u0, u1; v2, v3 share u1, u2; no V pair spans both
+    assert oracle.tip_components(g, 1, tv, 1).tolist() == [0, 0, 2, 2]
+
+
+def test_components_nest_across_levels():
+    """Every (k+1)-tip lies inside one k-tip, and likewise for wings (the
+    hierarchy of Section 2.2); a complete bipartite graph is one component
+    at every level up to its entity number."""
+    g = synth.chung_lu(400, 120, 2500, 2.1, 100, seed=21)
+    for side in (0, 1):
+        th = oracle.tip(g, side)
+        levels = sorted(set(th.tolist()))[::7]
+        prev = None
+        for k in levels:
+            cur = oracle.tip_components(g, side, th, k)
+            if prev is not None:
+                for c in np.unique(cur[cur >= 0]):
+                    assert len(np.unique(prev[cur == c])) == 1
+            prev = cur
+    tw = oracle.wing(g)
+    prev = None
+    for k in sorted(set(tw.tolist()))[::5]:
+        cur = oracle.wing_components(g, tw, k)
+        if prev is not None:
+            for c in np.unique(cur[cur >= 0]):
+                assert len(np.unique(prev[cur == c])) == 1
+        prev = cur
+    kab = synth.complete(4, 5)
+    th = oracle.tip(kab, 0)
+    assert oracle.tip_components(kab, 0, th, int(th[0])).tolist() == [0] * 4
+    tw = oracle.wing(kab)
+    assert oracle.wing_components(kab, tw, int(tw[0])).tolist() == [0] * 20
