@@ -252,6 +252,24 @@ int pbng_tip_schedule(pbng_ctx *ctx, const pbng_csr *g, pbng_side side,
 int pbng_wing(pbng_ctx *ctx, const pbng_csr *g, const pbng_opts *opts,
               uint64_t *wing_out);
 
+/* ---- Hierarchy retrieval (Section 2.2, Definitions 1-2) -------------------
+ *
+ * The k-tips of one side are the butterfly-connected components of its
+ * vertices with tip number >= k (with all of the other side): two vertices
+ * are joined when they share at least two neighbours, i.e. lie in a common
+ * butterfly.  The k-wings are the butterfly-connected components of the
+ * edges with wing number >= k: two edges are joined when a butterfly whose
+ * four edges all have wing number >= k holds both.  theta: the entity
+ * numbers from pbng_tip (uint64[n_side]) or pbng_wing (uint64[m]); comp_out:
+ * int32 of the same length, the smallest id in the entity's k-tip / k-wing,
+ * or -1 for entities below k.  Both in the graph's memory space.  Levels
+ * nest: every (k+1)-tip lies inside one k-tip, and likewise for wings.     */
+int pbng_tip_components(pbng_ctx *ctx, const pbng_csr *g, pbng_side side,
+                        const uint64_t *theta, uint64_t k, int32_t *comp_out);
+int pbng_wing_components(pbng_ctx *ctx, const pbng_csr *g,
+                         const uint64_t *theta, uint64_t k,
+                         int32_t *comp_out);
+
 /* ---- Many graphs per call ------------------------------------------------
  *
  * Tip numbers of one side / wing numbers of every edge of ng graphs.  A

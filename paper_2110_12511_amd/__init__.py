@@ -28,6 +28,8 @@ from .binding import (  # noqa: F401
     tip_batch,
     tip_schedule,
     tip_hinted,
+    tip_components,
+    wing_components,
     tip_features,
     wing_batch,
     to_numpy_u64,

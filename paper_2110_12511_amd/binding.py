@@ -118,7 +118,8 @@ class Stats(ctypes.Structure):
 EXPORTS = ["pbng_create", "pbng_destroy", "pbng_last_error", "pbng_last_stats", "pbng_count", "pbng_tip", "pbng_wing",
            "pbng_tip_features", "pbng_mlp_init", "pbng_mlp_set", "pbng_mlp_get", "pbng_mlp_forward",
            "pbng_mlp_loss_grad", "pbng_mlp_train", "pbng_tip_batch", "pbng_wing_batch", "pbng_autotune",
-           "pbng_tip_schedule", "pbng_predictor_load", "pbng_count_noalloc", "pbng_tip_hinted"]
+           "pbng_tip_schedule", "pbng_predictor_load", "pbng_count_noalloc", "pbng_tip_hinted",
+           "pbng_tip_components", "pbng_wing_components"]
 MLP_NPARAM = 8961
 
 _lib = None
@@ -171,6 +172,8 @@ def load():
                               ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
         "pbng_predictor_load": [vp, ctypes.c_char_p],
         "pbng_tip_hinted": [vp, ctypes.POINTER(Csr), ctypes.c_int, ctypes.POINTER(Opts), vp, vp],
+        "pbng_tip_components": [vp, ctypes.POINTER(Csr), ctypes.c_int, vp, ctypes.c_uint64, vp],
+        "pbng_wing_components": [vp, ctypes.POINTER(Csr), vp, ctypes.c_uint64, vp],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -340,6 +343,29 @@ def tip(ctx: Context, dg: DeviceGraph, side: int, opts: Opts | None = None):
     out = _out_tensor(n)
     ctx.tip_raw(dg.csr(), side, out.data_ptr(), opts)
     return out[:n]
+
+
+def tip_components(ctx: Context, dg: DeviceGraph, side: int, theta, k: int):
+    """k-tips of one side from its tip numbers (uint64 device tensor): int32
+    device tensor, smallest vertex id of each vertex's k-tip or -1."""
+    import torch
+
+    n = dg.n_u if side == SIDE_U else dg.n_v
+    out = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
+    ctx._check(ctx.lib.pbng_tip_components(ctx.h, ctypes.byref(dg.csr()), side, ctypes.c_void_p(theta.data_ptr()),
+                                           ctypes.c_uint64(int(k)), ctypes.c_void_p(out.data_ptr())))
+    return out[:n]
+
+
+def wing_components(ctx: Context, dg: DeviceGraph, theta, k: int):
+    """k-wings from the wing numbers (uint64 device tensor): int32 device
+    tensor, smallest edge id of each edge's k-wing or -1."""
+    import torch
+
+    out = torch.empty(max(dg.m, 1), dtype=torch.int32, device="cuda")
+    ctx._check(ctx.lib.pbng_wing_components(ctx.h, ctypes.byref(dg.csr()), ctypes.c_void_p(theta.data_ptr()),
+                                            ctypes.c_uint64(int(k)), ctypes.c_void_p(out.data_ptr())))
+    return out[: dg.m]
 
 
 def tip_hinted(ctx: Context, dg: DeviceGraph, side: int, hint, opts: Opts | None = None):

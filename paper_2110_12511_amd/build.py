@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libpbng.so")
-SOURCES = ["prims.hip", "prep.hip", "count.hip", "select.hip", "tip.hip", "wing.hip", "mfma.hip", "learned.hip", "batch.hip", "pbng_api.hip"]
+SOURCES = ["prims.hip", "prep.hip", "count.hip", "select.hip", "tip.hip", "wing.hip", "mfma.hip", "learned.hip", "batch.hip", "hier.hip", "pbng_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

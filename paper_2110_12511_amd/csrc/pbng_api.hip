@@ -440,6 +440,53 @@ int pbng_tip_schedule(pbng_ctx *x, const pbng_csr *g, pbng_side side, const pbng
     });
 }
 
+namespace pbng {
+namespace {
+int components_call(pbng_ctx *x, const pbng_csr *g, int what, const uint64_t *theta, uint64_t k, int32_t *comp) {
+    if (!x) return PBNG_E_ARG;
+    Ctx &c = x->c;
+    int rc = check_csr(g);
+    if (rc) return fail(c, rc, "bad graph arguments");
+    const i64 n = what == 2 ? g->m : (what == 0 ? g->n_u : g->n_v);
+    if (n > 0 && (!theta || !comp)) return fail(c, PBNG_E_ARG, "null entity numbers or output");
+    CallScope scope(c);
+    return guarded(c, [&] {
+        auto t0 = std::chrono::steady_clock::now();
+        c.timing_begin_call(false);
+        const bool host = !g->on_device;
+        pbng_csr dg = device_graph(c, *g);
+        const u64 *th = theta;
+        i32 *out = comp;
+        if (host && n > 0) {
+            u64 *t = c.alloc<u64>(n);
+            PBNG_HIP(hipMemcpyAsync(t, theta, sizeof(u64) * n, hipMemcpyHostToDevice, c.stream));
+            th = t;
+            out = c.alloc<i32>(n);
+        }
+        DevGraph G;
+        build_graph(c, dg, G);
+        level_components(c, G, what, th, k, out);
+        if (host && n > 0) PBNG_HIP(hipMemcpyAsync(comp, out, sizeof(i32) * n, hipMemcpyDeviceToHost, c.stream));
+        PBNG_HIP(hipStreamSynchronize(c.stream));
+        c.stats.ms_total = ms_since(t0);
+    });
+}
+}  // namespace
+}  // namespace pbng
+
+int pbng_tip_components(pbng_ctx *x, const pbng_csr *g, pbng_side side, const uint64_t *theta, uint64_t k,
+                        int32_t *comp_out) {
+    if (side != PBNG_SIDE_U && side != PBNG_SIDE_V) {
+        if (x) x->c.last_error = "bad side";
+        return PBNG_E_ARG;
+    }
+    return components_call(x, g, side == PBNG_SIDE_U ? 0 : 1, theta, k, comp_out);
+}
+
+int pbng_wing_components(pbng_ctx *x, const pbng_csr *g, const uint64_t *theta, uint64_t k, int32_t *comp_out) {
+    return components_call(x, g, 2, theta, k, comp_out);
+}
+
 int pbng_wing(pbng_ctx *x, const pbng_csr *g, const pbng_opts *opts, uint64_t *wing_out) {
     if (!x) return PBNG_E_ARG;
     Ctx &c = x->c;

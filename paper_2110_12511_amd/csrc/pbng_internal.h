@@ -178,6 +178,9 @@ void build_be_index(Ctx &c, const DevGraph &G, BEIndex &I, u64 *sup_edge);
 // ---- decompositions ----
 void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 *theta_dev);
 void wing_decompose(Ctx &c, const DevGraph &G, const pbng_opts &o, u64 *theta_dev);
+// k-tips (what 0: side U, 1: side V) or k-wings (what 2) from entity numbers
+// theta: comp[i] = smallest id of entity i's component at level k, or -1
+void level_components(Ctx &c, const DevGraph &G, int what, const u64 *theta, u64 k, i32 *comp);
 
 // ---- range selection (select.hip) ----
 // Smallest s with sum{w_l : active_l, key_l <= s} >= target; if the total is
