@@ -40,7 +40,11 @@ def test_profile_traffic_lookup(tmp_path, monkeypatch):
 
 
 def test_committed_summary_is_well_formed():
-    path = os.path.join(ROOT, "profiles", "k_tip_peel_tiled__tip_cl_1m_200k_20m.md")
+    path = os.path.join(ROOT, "profiles", "k_tip_peel_hrange__tip_u_cl_5m_1m_100m.md")
     text = open(path).read()
     assert "traffic_bytes_per_launch:" in text and "source_sha256:" in text
     assert "rocprofv3 --kernel-trace --stats" in text and "--pmc FETCH_SIZE" in text and "--pmc WRITE_SIZE" in text
+    # the summary was taken on the current kernel sources
+    import bench
+
+    assert bench.profile_traffic("tip_hrange", "tip_u_cl_5m_1m_100m") is not None
