@@ -3,15 +3,16 @@
 
 Default workload: tip decomposition of side U of the seeded Chung-Lu graph
 |U|=5M, |V|=1M, 100M edges, exponent 2.0, degree cap 50k, P=150 -- the
-held-out graph on which learned and plain range bounds are compared.  A step
-is one call: preprocessing, priority counting, coarse-grained peel rounds
-(replayed from a captured HIP graph, with recounts) and the fine-grained
-persistent kernel, all on the GPU with the graph resident in HBM before the
-timed region.
+held-out graph on which learned and plain range bounds are compared -- under
+the paper's range-bound rule.  A step is one call: preprocessing, priority
+counting, coarse-grained peel rounds (replayed from a captured HIP graph,
+with recounts) and the fine-grained persistent kernel, all on the GPU with the
+graph resident in HBM before the timed region.
 
 Prints one JSON line: wedges/s over the timed steps (value), the per-step
-decomposition time, the bound rules compared on the same graph (the library's
-plain rule, the paper's rule alone, learned), the roofline of the dominant
+decomposition time, the bound rules compared on the same graph (the paper's
+rule, the library's plain rule, learned, learned with perfect predictions),
+the roofline of the dominant
 kernel class (algorithmic bytes / its HIP-event time on the library's stream,
 from a kernel-timing pass), the 20M-edge tip and 5M-edge wing workloads as
 extra keys, and the CPU oracle timed on a bounded sample.
@@ -235,7 +236,7 @@ def side_entry(pb, st, q, res, graph_cfg, ref=None):
              rho=st["rho"], partitions=st["partitions"], fd_imbalance=round(imb, 2), rule_used=st["bound_rule_used"],
              exact=(digest(pb.to_numpy_u64(res)) == rec["sha256"]) if rec else None)
     if ref is not None:
-        d["identical_to_plain"] = digest(pb.to_numpy_u64(res)) == ref
+        d["identical_to_paper_rule"] = digest(pb.to_numpy_u64(res)) == ref
     return d
 
 
@@ -261,9 +262,25 @@ def extra_workload(pb, torch, ctx, name, cache_dir):
     d = dict(workload=g.name, ms=round(ms, 2), wedges=wedges, wedges_per_s=round(wedges / (ms / 1e3), 1),
              phases_ms=[{k: round(s[k], 2) for k in ("ms_total", "ms_count", "ms_cd", "ms_fd_prep", "ms_fd")}
                         for s in stats],
-             rho=[s["rho"] for s in stats], parity_vs_oracle=parity)
+             rho=[s["rho"] for s in stats], bound_rule="plain", parity_vs_oracle=parity)
     if kind == "wing":
         d.update(updates=stats[0]["updates"], links=stats[0]["links"], blooms=stats[0]["blooms"])
+    # the paper's ablations (Section 6, Figs 6 and 9): PBNG- keeps peeled
+    # entities in the lists (no dynamic graph updates); PBNG-- also never
+    # recounts (tip; the wing's unbatched update is not built)
+    abl = {"PBNG": dict(ms=round(ms, 2), wedges=wedges, updates=sum(s["updates"] for s in stats))}
+    variants = [("PBNG-", pb.F_NO_DYNAMIC)]
+    if kind != "wing":
+        variants.append(("PBNG--", pb.F_NO_DYNAMIC | pb.F_NO_BATCH))
+    for vname, fl in variants:
+        t0 = time.perf_counter()
+        outs_v, stats_v = run_step(pb, ctx, dg, kind, P, fl)
+        torch.cuda.synchronize()
+        vms = (time.perf_counter() - t0) * 1e3
+        same = all(digest(pb.to_numpy_u64(a)) == digest(pb.to_numpy_u64(b)) for a, b in zip(outs, outs_v))
+        abl[vname] = dict(ms=round(vms, 2), wedges=sum(s["wedges"] for s in stats_v),
+                          updates=sum(s["updates"] for s in stats_v), identical=same)
+    d["ablation"] = abl
     del dg
     return d
 
@@ -312,9 +329,11 @@ def main():
     copy = copy_probe(torch)
     log(f"[bench] copy kernel: {copy['gbs']} GB/s")
 
-    # batches: learned bounds (when a predictor is stored) and the autotuner's
-    # hub cut-over and key-tile threshold, tuned on the largest graph
-    rule, tune, tuned = 0, None, None
+    # single graphs: the paper's bound rule (Section 3.1.3; the other rules
+    # are compared below).  Batches: learned bounds (when a predictor is
+    # stored) and the autotuner's hub cut-over and key-tile threshold, tuned
+    # on the largest graph.
+    rule, tune, tuned = (pb.BOUND_PAPER if kind in ("tip", "tip_u") else 0), None, None
     if kind == "batch":
         from paper_2110_12511_amd import predictor
 
@@ -402,7 +421,7 @@ def main():
                                 "P_used", "fd_work_max", "fd_work_sum", "updates", "links", "blooms")} for s in last]
 
     # bound rules on the same graph and P, outside the timed steps (tip
-    # workloads): the library's plain rule, the paper's rule alone, learned
+    # workloads): the paper's rule, the library's plain rule, learned
     rules = None
     if kind in ("tip", "tip_u") and not args.no_learned:
         from paper_2110_12511_amd import predictor
@@ -410,17 +429,17 @@ def main():
         have_pred = predictor.install(ctx)
         rules = {}
         ref = {}
-        for rule_name, rule in (("plain", pb.BOUND_PLAIN), ("paper", pb.BOUND_PAPER), ("learned", pb.BOUND_LEARNED)):
+        for rule_name, rrule in (("paper", pb.BOUND_PAPER), ("plain", pb.BOUND_PLAIN), ("learned", pb.BOUND_LEARNED)):
             if rule_name == "learned" and not have_pred:
                 continue
             per_side = []
             for side in ((pb.SIDE_U, pb.SIDE_V) if kind == "tip" else (pb.SIDE_U,)):
-                t = pb.tip(ctx, dg, side, pb.make_opts(P=P, bound_rule=rule))
+                t = pb.tip(ctx, dg, side, pb.make_opts(P=P, bound_rule=rrule))
                 torch.cuda.synchronize()
                 q = "tip_u" if side == pb.SIDE_U else "tip_v"
-                if rule_name == "plain":
+                if rule_name == "paper":
                     ref[q] = digest(pb.to_numpy_u64(t))
-                per_side.append(side_entry(pb, ctx.stats(), q, t, graph_cfg, ref.get(q) if rule_name != "plain" else None))
+                per_side.append(side_entry(pb, ctx.stats(), q, t, graph_cfg, ref.get(q) if rule_name != "paper" else None))
             rules[rule_name] = per_side
             log(f"[bench] bound rule {rule_name}: " + ", ".join(f"{e['side']} {e['ms_total']} ms" for e in per_side))
         # the learned rule with perfect predictions (the exact tip numbers as
@@ -428,7 +447,7 @@ def main():
         per_side = []
         for side in ((pb.SIDE_U, pb.SIDE_V) if kind == "tip" else (pb.SIDE_U,)):
             q = "tip_u" if side == pb.SIDE_U else "tip_v"
-            exact = pb.tip(ctx, dg, side, pb.make_opts(P=P))
+            exact = pb.tip(ctx, dg, side, pb.make_opts(P=P, bound_rule=pb.BOUND_PAPER))
             t = pb.tip_hinted(ctx, dg, side, exact, pb.make_opts(P=P))
             torch.cuda.synchronize()
             per_side.append(side_entry(pb, ctx.stats(), q, t, graph_cfg, ref.get(q)))
@@ -465,13 +484,15 @@ def main():
         "config": {"workload": {"tip": "tip decomposition (both sides)", "tip_u": "tip decomposition (side U)",
                                 "wing": "wing decomposition (all edges)",
                                 "batch": "batched tip (side U) and wing decompositions"}[kind] + f" of {g.name}",
-                   "graph": graph_cfg, "P": P, "bound_rule": "plain", "m": g_m, "n_u": g.n_u, "n_v": g.n_v},
+                   "graph": graph_cfg, "P": P,
+                   "bound_rule": {pb.BOUND_PAPER: "paper", pb.BOUND_LEARNED: "learned"}.get(rule, "plain"), "m": g_m,
+                   "n_u": g.n_u, "n_v": g.n_v},
         "decomposition_ms": round(min(step_ms), 2),
         "phases_ms": phases,
         "work": work,
         "roofline": roofline,
         "copy_kernel": copy,
-        "learned_vs_plain": rules,
+        "bound_rules": rules,
         "extras": extras,
         "cpu_baseline": cpu,
         "parity_vs_oracle": parity or None,
