@@ -36,7 +36,7 @@ sys.path.insert(0, ROOT)
 METRIC = "wedges/s + tip/wing decomposition time, learned vs plain CD bounds, 1 GPU"
 HBM_PEAK_GBS = 8000.0
 # kernel behind each timed class that holds a single kernel
-CLASS_KERNEL = {"tip_hrange": "k_tip_peel_hrange<14>", "tip_tiled": "k_tip_peel_tiled<16, true>",
+CLASS_KERNEL = {"tip_hrange": "k_tip_peel_hrange<13, 512>", "tip_tiled": "k_tip_peel_tiled<16, true>",
                 "fd": "k_tip_fd / k_wing_fd", "dense": "m_gram", "wing_cd": "w_links / w_blooms"}
 
 WORKLOADS = {

@@ -101,6 +101,11 @@ typedef enum {
                                     synchronisation per round, instead of
                                     replays of a captured HIP graph of
                                     several rounds                           */
+#define PBNG_F_SHORT_PROBE 0x20  /* tip: the key-range peel kernel gives up
+                                    after one LDS probe, so most of its
+                                    items take the exact HBM overflow pass
+                                    (a test hook for that path; results are
+                                    unchanged, only slower)                  */
 
 /* Kernel classes timed under PBNG_F_KERNEL_TIMING. */
 enum {

@@ -18,6 +18,7 @@ from .binding import (  # noqa: F401
     F_NO_DENSE_TILE,
     F_NO_DYNAMIC,
     F_HOST_ROUNDS,
+    F_SHORT_PROBE,
     Context,
     DeviceGraph,
     PbngError,

@@ -66,6 +66,7 @@ K_COUNT, K_TIP_PEEL, K_FD, K_WING_CD, K_DENSE, K_TIP_HRANGE, K_TIP_TILED, K_NCLA
 K_NAMES = ["count", "tip_peel", "fd", "wing_cd", "dense", "tip_hrange", "tip_tiled"]
 F_KERNEL_TIMING = 0x8
 F_HOST_ROUNDS = 0x10
+F_SHORT_PROBE = 0x20
 
 
 class KernelStat(ctypes.Structure):

@@ -71,8 +71,10 @@ constexpr int TIP_GRAPH_K = 2;
 constexpr int TILE_LOG = 16;
 // active vertices with more wedges than this take the key-tile path
 constexpr i64 HUGE_W = i64(1) << 16;
-// LDS hash slots of the (vertex, key range) path
-constexpr int H_LOGCAP = 14;
+// LDS hash slots of the (vertex, key range) path, and its workgroups per CU
+constexpr int H_LOGCAP = 13;
+constexpr int H_BLOCK = 512;
+constexpr int H_WG_PER_CU = 2;
 // active vertices with 2..PAIR_DMAX neighbours whose pairwise list
 // intersections cost less than 1 / PAIR_COST of their wedges take that path
 constexpr i64 PAIR_DMAX = 8;
@@ -101,9 +103,10 @@ struct PeelArgs {
     const u64 *bound;
     i32 *nf;
     u32 *nnf;
-    u32 *dcnt;
-    i32 *dtouch;
-    u32 *dntouch;
+    u32 *dcnt;           // key-range overflow: HBM counters (nx, zero between holders)
+    i32 *dtouch;         // their touched keys (nx)
+    u32 *dlock;          // the lock that serialises their holders
+    i32 hprobe;          // LDS probe limit of the key-range path
     i32 ntiles;
     i64 nx;
     u64 *tnext;          // key-tile item counter
@@ -189,6 +192,61 @@ __device__ __forceinline__ void run_ends(const i32 *yadj, const i32 *pre, const 
 #pragma unroll
     for (int q = 0; q < UNR; ++q)
         if (k0 + q >= tot) xq[q] = x;
+}
+
+// Probe of one step of a lower-bound search over a[lo, hi) whose keys lie
+// in [vlo, vhi) and which holds k in that range: the interpolated position
+// while interp is set (keys spread evenly over the id space land within a
+// few slots), the midpoint otherwise.
+__device__ __forceinline__ i64 lb_probe(i64 lo, i64 hi, i64 vlo, i64 vhi, i64 k, bool interp) {
+    i64 p;
+    if (interp && vhi > vlo)
+        p = lo + (i64)((u64)(k - vlo) * (u64)(hi - lo) / (u64)(vhi - vlo));
+    else
+        p = (lo + hi) >> 1;
+    return p < hi ? p : hi - 1;
+}
+
+// Steps of a search that interpolate; later steps halve, so a search takes
+// at most LB_INTERP + log2(run) + 1 dependent loads for any key spread.
+constexpr int LB_INTERP = 6;
+
+// The run of a sorted, duplicate-free live list a[base, end) of X ids
+// (below nx) with ids in [k0, k1): p0 = first slot with id >= k0, p1 =
+// first slot with id >= k1 (k0 <= k1; k0 <= 0 gives base, k1 >= nx gives
+// end).  The two searches advance in lockstep, so the loads of one step of
+// both are in flight together; each keeps the key interval of its slot
+// interval, [vlo, vhi), for the interpolation.
+__device__ __forceinline__ void run_bounds(const i32 *a, i64 base, i64 end, i64 nx, i64 k0, i64 k1, i64 &p0, i64 &p1) {
+    i64 lo0 = base, hi0 = k0 > 0 ? end : base, vl0 = 0, vh0 = nx;
+    i64 lo1 = k1 < nx ? base : end, hi1 = end, vl1 = 0, vh1 = nx;
+    for (int it = 0; lo0 < hi0 || lo1 < hi1; ++it) {
+        const bool ip = it < LB_INTERP;
+        const bool a0 = lo0 < hi0, a1 = lo1 < hi1;
+        const i64 q0 = a0 ? lb_probe(lo0, hi0, vl0, vh0, k0, ip) : 0;
+        const i64 q1 = a1 ? lb_probe(lo1, hi1, vl1, vh1, k1, ip) : 0;
+        const i64 v0 = a0 ? a[q0] : 0, v1 = a1 ? a[q1] : 0;
+        if (a0) {
+            if (v0 < k0) {
+                lo0 = q0 + 1;
+                vl0 = v0 + 1;
+            } else {
+                hi0 = q0;
+                vh0 = v0;
+            }
+        }
+        if (a1) {
+            if (v1 < k1) {
+                lo1 = q1 + 1;
+                vl1 = v1 + 1;
+            } else {
+                hi1 = q1;
+                vh1 = v1;
+            }
+        }
+    }
+    p0 = lo0;
+    p1 = lo1;
 }
 
 // next active set of a push round: alive vertices below the bound (none
@@ -327,13 +385,15 @@ __global__ __launch_bounds__(512) void k_tip_peel_tiled(PeelArgs a, int bin) {
     const u64 n = (u64)a.nitems[bin] * nt;
     const u64 B = *a.bound;
     Tally tl;
+    // the last wave claims the next item while the others start this one
+    constexpr int CLAIM = BLOCK - WAVE;
+    if (threadIdx.x == CLAIM) s_item = atomicAdd((unsigned long long *)a.tnext, 1ull);
     __syncthreads();
     for (;;) {
-        if (threadIdx.x == 0) s_item = atomicAdd((unsigned long long *)a.tnext, 1ull);
-        __syncthreads();
         const u64 item = s_item;
         __syncthreads();
         if (item >= n) break;
+        if (threadIdx.x == CLAIM) s_item = atomicAdd((unsigned long long *)a.tnext, 1ull);
         const i32 x = a.items[item / nt];
         const u32 t = (u32)(item % nt);
         const i64 r0 = (i64)t << TLOG;
@@ -352,23 +412,8 @@ __global__ __launch_bounds__(512) void k_tip_peel_tiled(PeelArgs a, int bin) {
             if (j < d) {
                 const i32 y = a.xadj[jb + j];
                 const i64 base = a.yrow[y];
-                const i64 end = base + a.ylen[y];
-                i64 lo = base, hi = end;
-                if (r0 > 0) {
-                    while (lo < hi) {
-                        const i64 md = (lo + hi) >> 1;
-                        if ((i64)a.yadj[md] < r0) lo = md + 1; else hi = md;
-                    }
-                }
-                i64 e = end;
-                if (r1 < a.nx) {
-                    i64 l2 = lo, h2 = end;
-                    while (l2 < h2) {
-                        const i64 md = (l2 + h2) >> 1;
-                        if ((i64)a.yadj[md] < r1) l2 = md + 1; else h2 = md;
-                    }
-                    e = l2;
-                }
+                i64 lo, e;
+                run_bounds(a.yadj, base, base + a.ylen[y], a.nx, r0, r1, lo, e);
                 pl = (i32)(e - lo);
                 moff = lo;
             }
@@ -397,8 +442,7 @@ __global__ __launch_bounds__(512) void k_tip_peel_tiled(PeelArgs a, int bin) {
             }
             __syncthreads();
         }
-        if (!any) continue;
-        const i32 nbw = (i32)(((r1 - r0 + KPW - 1) / KPW) + 31) >> 5;
+        const i32 nbw = any ? (i32)(((r1 - r0 + KPW - 1) / KPW) + 31) >> 5 : 0;
         for (i32 bw = threadIdx.x; bw < nbw; bw += BLOCK) {
             u32 bits = bm[bw];
             if (!bits) continue;
@@ -441,12 +485,13 @@ __global__ __launch_bounds__(512) void k_tip_peel_tiled(PeelArgs a, int bin) {
 // few neighbours with long lists, the common case under power-law degrees):
 // the wedges of x are cut into R_x = ceil(w_x / H_RANGE_W) ranges of the X
 // key space, and one work item is one (vertex, range) pair.  Each range
-// counts c(x, x') in an LDS hash table of 2^LOGCAP slots; the run of every
-// neighbour list inside the range is found by binary search (none when
-// R_x = 1).  A key whose probe sequence is full goes, for every occurrence,
-// to the workgroup's HBM counters with a touched list, so every key lives
-// wholly in one of the two and the result is exact for any key skew.
-constexpr i64 H_RANGE_W = 8192;
+// counts c(x, x') in an LDS hash table of 2^LOGCAP slots (twice the wedges
+// of an item whose keys are spread evenly, and small enough for two
+// workgroups per CU); the run of every neighbour list inside the range is
+// found by a lockstep search (none when R_x = 1).  An item one of whose keys
+// finds its probe sequence full is counted again in HBM (see the kernel), so
+// the result is exact for any key skew.
+constexpr i64 H_RANGE_W = 4096;
 constexpr u32 H_RANGE_MAX = 64;
 constexpr int H_PROBE = 64;
 
@@ -475,162 +520,243 @@ __global__ __launch_bounds__(1024) void k_range_split(const i32 *items, const u3
     }
 }
 
-template <int LOGCAP>
-__global__ __launch_bounds__(512) void k_tip_peel_hrange(PeelArgs a, int bin, const u32 *off, const u32 *total) {
-    constexpr int BLOCK = 512;
+// Item claim of the key-range path, run by one whole wave: the next item
+// index, then the vertex that owns it (the last h with off[h] <= item; off
+// is strictly increasing with off[nh] = n) by a 64-way search, one probe per
+// lane, so a few dependent loads resolve it, then its row and the live list
+// of each of its first 64 neighbours.  The result goes to LDS for the next
+// iteration, so those dependent loads leave the next item's critical path.
+struct RangeItem {
+    u32 item;
+    i32 x;
+    u32 r, R;
+    i64 jb;
+    i32 d;
+    i64 base[WAVE];  // live list of neighbour j < 64: start and length
+    i32 len[WAVE];
+};
+
+__device__ __forceinline__ void claim_range_item(const PeelArgs &a, int bin, const u32 *off, u32 nh, u32 n, RangeItem *out) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    u32 it = 0;
+    if (lane == 0) it = atomicAdd(&a.next[bin], 1u);
+    it = __shfl(it, 0, WAVE);
+    if (it < n) {
+        u32 lo = 0, hi = nh - 1;
+        while (lo < hi) {
+            const u32 span = hi - lo;
+            const u32 p = lo + (u32)(((u64)(lane + 1) * span + WAVE - 1) / WAVE);
+            const int c = __popcll(__ballot(off[p] <= it));
+            const u32 nlo = c ? lo + (u32)(((u64)c * span + WAVE - 1) / WAVE) : lo;
+            const u32 nhi = c < WAVE ? lo + (u32)(((u64)(c + 1) * span + WAVE - 1) / WAVE) - 1 : hi;
+            lo = nlo;
+            hi = nhi;
+        }
+        const i32 x = a.items[lo];
+        const i64 jb = a.xrow[x];
+        const i32 d = (i32)(a.xrow[x + 1] - jb);
+        if (lane < d) {
+            const i32 y = a.xadj[jb + lane];
+            out->base[lane] = a.yrow[y];
+            out->len[lane] = a.ylen[y];
+        }
+        if (lane == 0) {
+            out->x = x;
+            out->r = it - off[lo];
+            out->R = off[lo + 1] - off[lo];
+            out->jb = jb;
+            out->d = d;
+        }
+    }
+    if (lane == 0) out->item = it;
+}
+
+template <int LOGCAP, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_tip_peel_hrange(PeelArgs a, int bin, const u32 *off, const u32 *total) {
     constexpr u32 CAP = 1u << LOGCAP;
     __shared__ i32 keys[CAP];
     __shared__ u32 vals[CAP];
     __shared__ i32 s_pre[BLOCK];
     __shared__ i64 s_moff[BLOCK];
     __shared__ i32 s_wave[BLOCK / WAVE];
-    __shared__ u32 s_item, s_ntouch;
+    __shared__ u32 s_ntouch, s_ovf;
+    __shared__ RangeItem s_it[2];
     for (u32 i = threadIdx.x; i < CAP; i += BLOCK) {
         keys[i] = -1;
         vals[i] = 0;
     }
-    if (threadIdx.x == 0) s_ntouch = 0;
-    u32 *gc = a.dcnt + (i64)blockIdx.x * a.nx;
-    i32 *touch = a.dtouch + (i64)blockIdx.x * a.nx;
+    if (threadIdx.x == 0) {
+        s_ntouch = 0;
+        s_ovf = 0;
+    }
     const u32 nh = a.nitems[bin];
     const u32 n = *total;
     const u64 B = *a.bound;
+    const int probe = a.hprobe;
     Tally tl;
+    // the last wave claims and resolves the next item into the other
+    // buffer while the others start this one
+    const bool claimer = threadIdx.x >= BLOCK - WAVE;
+    int cur = 0;
+    if (claimer) claim_range_item(a, bin, off, nh, n, &s_it[0]);
     __syncthreads();
-    for (;;) {
-        if (threadIdx.x == 0) s_item = atomicAdd(&a.next[bin], 1u);
-        __syncthreads();
-        const u32 item = s_item;
-        __syncthreads();
+    for (;; cur ^= 1) {
+        const RangeItem &ci = s_it[cur];
+        const u32 item = ci.item;
         if (item >= n) break;
-        // owning vertex: last h with off[h] <= item
-        u32 lo = 0, hi = nh - 1;
-        while (lo < hi) {
-            const u32 md = (lo + hi + 1) >> 1;
-            if (off[md] <= item) lo = md; else hi = md - 1;
-        }
-        const i32 x = a.items[lo];
-        const u32 r = item - off[lo];
-        const u32 R = off[lo + 1] - off[lo];
+        if (claimer) claim_range_item(a, bin, off, nh, n, &s_it[cur ^ 1]);
+        const i32 x = ci.x;
+        const u32 r = ci.r, R = ci.R;
         const i64 k0 = (i64)r * a.nx / R, k1 = (i64)(r + 1) * a.nx / R;
-        const i64 jb = a.xrow[x];
-        const i32 d = (i32)(a.xrow[x + 1] - jb);
+        const i64 jb = ci.jb;
+        const i32 d = ci.d;
         if (threadIdx.x == 0 && r == 0) {
             tl.segments += (u64)d;
             tl.items += 1;
         }
-        for (i32 cb = 0; cb < d; cb += BLOCK) {
-            const i32 j = cb + threadIdx.x;
-            i32 pl = 0;
-            i64 moff = 0;
-            if (j < d) {
-                const i32 y = a.xadj[jb + j];
-                const i64 base = a.yrow[y];
-                const i64 end = base + a.ylen[y];
-                i64 b0 = base, e = end;
-                if (k0 > 0) {
-                    i64 h2 = end;
-                    while (b0 < h2) {
-                        const i64 md = (b0 + h2) >> 1;
-                        if ((i64)a.yadj[md] < k0) b0 = md + 1; else h2 = md;
-                    }
+        // Pass 0 counts in the LDS table.  If a key finds its probe
+        // sequence full, the item's LDS counts are dropped and pass 1
+        // counts the whole item again in the HBM counters, which all
+        // workgroups share under a lock (one item at a time; the counters
+        // are zero between holders), so the result is exact for any key skew.
+        bool redo = false;
+        for (int pass = 0; pass < 2; ++pass) {
+            if (pass == 1) {
+                if (!redo) break;  // block-uniform
+                if (threadIdx.x == 0) {
+                    while (atomicCAS(a.dlock, 0u, 1u) != 0u) __builtin_amdgcn_s_sleep(8);
+                    __threadfence();
                 }
-                if (k1 < a.nx) {
-                    i64 l2 = b0;
-                    while (l2 < e) {
-                        const i64 md = (l2 + e) >> 1;
-                        if ((i64)a.yadj[md] < k1) l2 = md + 1; else e = md;
-                    }
-                }
-                pl = (i32)(e - b0);
-                moff = b0;
+                __syncthreads();
             }
-            i32 tot;
-            const i32 incl = block_incl_scan_i32<BLOCK>(pl, s_wave, tot);
-            if (tot == 0) continue;  // block-uniform
-            s_pre[threadIdx.x] = incl;
-            s_moff[threadIdx.x] = moff;
-            __syncthreads();
-            const int last = (d - cb < BLOCK ? d - cb : BLOCK) - 1;
-            constexpr int UNR = 8;
-            for (i32 kb = 0; kb < tot; kb += UNR * BLOCK) {
-                i32 xq[UNR];
-                run_ends<UNR>(a.yadj, s_pre, s_moff, last, kb + (i32)threadIdx.x * UNR, tot, x, xq);
-                // Linear probing over H_PROBE slots.  The first probe of all
-                // UNR keys is one batch of compare-and-swaps issued together
-                // (claim the home slot if empty; a skipped wedge compares
-                // against -2, which no slot holds, so it writes nothing), so
-                // most keys settle after one LDS round trip shared by the
-                // batch; the rest continue one by one from the next slot.
-                u32 hs[UNR];
-                i32 kk[UNR];
-#pragma unroll
-                for (int q = 0; q < UNR; ++q) {
-                    hs[q] = hash32((u32)xq[q]) >> (32 - LOGCAP);
-                    kk[q] = atomicCAS(&keys[hs[q]], xq[q] != x ? -1 : -2, xq[q]);
-                }
-#pragma unroll
-                for (int q = 0; q < UNR; ++q)
-                    if (kk[q] == -1) kk[q] = xq[q];
-#pragma unroll
-                for (int q = 0; q < UNR; ++q) {
-                    const i32 xp = xq[q];
-                    if (xp == x) continue;
-                    ++tl.wedges;
-                    u32 h = hs[q];
-                    bool done = kk[q] == xp;
-                    for (int p = 1; p < H_PROBE && !done; ++p) {
-                        h = (h + 1) & (CAP - 1);
-                        const i32 k2 = keys[h];
-                        if (k2 == xp) {
-                            done = true;
-                        } else if (k2 == -1) {
-                            const i32 prev = atomicCAS(&keys[h], -1, xp);
-                            done = prev == -1 || prev == xp;
-                        }
-                    }
-                    if (done) {
-                        atomicAdd(&vals[h], 1u);
+            for (i32 cb = 0; cb < d; cb += BLOCK) {
+                const i32 j = cb + threadIdx.x;
+                i32 pl = 0;
+                i64 moff = 0;
+                if (j < d) {
+                    i64 base;
+                    i32 len;
+                    if (j < WAVE) {
+                        base = ci.base[j];
+                        len = ci.len[j];
                     } else {
-                        const u32 old = __hip_atomic_fetch_add(&gc[xp], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        if (old == 0) {
-                            const u32 t = atomicAdd(&s_ntouch, 1u);
-                            __hip_atomic_store(&touch[t], xp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        const i32 y = a.xadj[jb + j];
+                        base = a.yrow[y];
+                        len = a.ylen[y];
+                    }
+                    i64 b0, e;
+                    run_bounds(a.yadj, base, base + len, a.nx, k0, k1, b0, e);
+                    pl = (i32)(e - b0);
+                    moff = b0;
+                }
+                i32 tot;
+                const i32 incl = block_incl_scan_i32<BLOCK>(pl, s_wave, tot);
+                if (tot == 0) continue;  // block-uniform
+                s_pre[threadIdx.x] = incl;
+                s_moff[threadIdx.x] = moff;
+                __syncthreads();
+                const int last = (d - cb < BLOCK ? d - cb : BLOCK) - 1;
+                constexpr int UNR = 8;
+                for (i32 kb = 0; kb < tot; kb += UNR * BLOCK) {
+                    i32 xq[UNR];
+                    run_ends<UNR>(a.yadj, s_pre, s_moff, last, kb + (i32)threadIdx.x * UNR, tot, x, xq);
+                    if (pass == 1) {
+#pragma unroll
+                        for (int q = 0; q < UNR; ++q) {
+                            const i32 xp = xq[q];
+                            if (xp == x) continue;
+                            const u32 old = __hip_atomic_fetch_add(&a.dcnt[xp], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            if (old == 0) {
+                                const u32 t = atomicAdd(&s_ntouch, 1u);
+                                __hip_atomic_store(&a.dtouch[t], xp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            }
                         }
+                        continue;
+                    }
+                    // Linear probing over the first `probe` slots.  The first
+                    // probe of all UNR keys is one batch of compare-and-swaps
+                    // issued together (claim the home slot if empty; a
+                    // skipped wedge compares against -2, which no slot holds,
+                    // so it writes nothing), so most keys settle after one
+                    // LDS round trip shared by the batch; the rest continue
+                    // one by one from the next slot.
+                    u32 hs[UNR];
+                    i32 kk[UNR];
+#pragma unroll
+                    for (int q = 0; q < UNR; ++q) {
+                        hs[q] = hash32((u32)xq[q]) >> (32 - LOGCAP);
+                        kk[q] = atomicCAS(&keys[hs[q]], xq[q] != x ? -1 : -2, xq[q]);
+                    }
+#pragma unroll
+                    for (int q = 0; q < UNR; ++q)
+                        if (kk[q] == -1) kk[q] = xq[q];
+#pragma unroll
+                    for (int q = 0; q < UNR; ++q) {
+                        const i32 xp = xq[q];
+                        if (xp == x) continue;
+                        ++tl.wedges;
+                        u32 h = hs[q];
+                        bool done = kk[q] == xp;
+                        for (int p = 1; p < probe && !done; ++p) {
+                            h = (h + 1) & (CAP - 1);
+                            const i32 k2 = keys[h];
+                            if (k2 == xp) {
+                                done = true;
+                            } else if (k2 == -1) {
+                                const i32 prev = atomicCAS(&keys[h], -1, xp);
+                                done = prev == -1 || prev == xp;
+                            }
+                        }
+                        if (done)
+                            atomicAdd(&vals[h], 1u);
+                        else
+                            s_ovf = 1;
                     }
                 }
+                __syncthreads();
             }
-            __syncthreads();
-        }
-        // epilogue: LDS entries, then keys that overflowed to HBM
-        constexpr int NB = 8;
-        for (u32 i0 = threadIdx.x; i0 < CAP; i0 += NB * BLOCK) {
-            i32 kk[NB];
-            u32 cc[NB];
+            if (pass == 0) {
+                // the LDS entries: applied, or dropped when the item overflowed
+                redo = s_ovf != 0;
+                constexpr int NB = 8;
+                for (u32 i0 = threadIdx.x; i0 < CAP; i0 += NB * BLOCK) {
+                    i32 kk[NB];
+                    u32 cc[NB];
 #pragma unroll
-            for (int q = 0; q < NB; ++q) {
-                const u32 i = i0 + q * BLOCK;
-                kk[q] = keys[i];
-                cc[q] = vals[i];
-                keys[i] = -1;
-                vals[i] = 0;
-            }
-            apply_updates<NB>(a, B, kk, cc, tl);
-        }
-        const u32 nt = s_ntouch;
-        for (u32 i0 = threadIdx.x; i0 < nt; i0 += 4 * BLOCK) {
-            i32 kk[4];
-            u32 cc[4];
+                    for (int q = 0; q < NB; ++q) {
+                        const u32 i = i0 + q * BLOCK;
+                        kk[q] = redo ? -1 : keys[i];
+                        cc[q] = vals[i];
+                        keys[i] = -1;
+                        vals[i] = 0;
+                    }
+                    apply_updates<NB>(a, B, kk, cc, tl);
+                }
+                __syncthreads();
+                if (threadIdx.x == 0) s_ovf = 0;
+            } else {
+                // the touched HBM counters, cleared for the next holder
+                const u32 nt = s_ntouch;
+                for (u32 i0 = threadIdx.x; i0 < nt; i0 += 4 * BLOCK) {
+                    i32 kk[4];
+                    u32 cc[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const u32 i = i0 + q * BLOCK;
-                kk[q] = i < nt ? __hip_atomic_load(&touch[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : -1;
-                cc[q] = kk[q] >= 0 ? __hip_atomic_exchange(&gc[kk[q]], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+                    for (int q = 0; q < 4; ++q) {
+                        const u32 i = i0 + q * BLOCK;
+                        kk[q] = i < nt ? __hip_atomic_load(&a.dtouch[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : -1;
+                        cc[q] = kk[q] >= 0 ? __hip_atomic_exchange(&a.dcnt[kk[q]], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                           : 0u;
+                    }
+                    apply_updates<4>(a, B, kk, cc, tl);
+                }
+                __threadfence();
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    s_ntouch = 0;
+                    atomicExch(a.dlock, 0u);
+                }
             }
-            apply_updates<4>(a, B, kk, cc, tl);
         }
-        __syncthreads();
-        if (threadIdx.x == 0) s_ntouch = 0;
     }
     tl.flush(a.kc, a.wedges);
 }
@@ -992,8 +1118,10 @@ __global__ void k_degrees_y(const i64 *yrow, i64 ny, i32 *ydeg, i32 *ylen) {
     }
 }
 
-// Seeded random bounds (schedule-invariance tests): theta(i+1) drawn between
-// the smallest alive support + 1 and the largest alive support + 1.
+// Smallest and largest alive support (grid-stride, one atomic pair per
+// wave; launched with a capped grid so the two counters see few atomics).
+// Seeded random bounds (schedule-invariance tests) draw theta(i+1) between
+// them; single levels and the learned guard use the smallest.
 __global__ void k_random_bound(const u64 *sup, const unsigned char *st, i64 nx, u64 *mn, u64 *mx) {
     u64 a = ~0ull, b = 0;
     for (i64 x = blockIdx.x * (i64)blockDim.x + threadIdx.x; x < nx; x += (i64)gridDim.x * blockDim.x) {
@@ -1580,12 +1708,14 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
         PBNG_HIP(hipMemcpyAsync(&ctl->scale, &one, sizeof(double), hipMemcpyHostToDevice, s));
     }
     // dense scratch for heavy active vertices
-    const int slots = c.num_cu;
-    u32 *dcnt = c.alloc<u32>((i64)slots * nx);
-    i32 *dtouch = c.alloc<i32>((i64)slots * nx);
-    u32 *dntouch = c.alloc<u32>(slots);
-    PBNG_HIP(hipMemsetAsync(dcnt, 0, sizeof(u32) * slots * nx, s));
-    PBNG_HIP(hipMemsetAsync(dntouch, 0, sizeof(u32) * slots, s));
+    // key-range path: H_WG_PER_CU workgroups per CU, one shared set of
+    // overflow counters
+    const int slots = H_WG_PER_CU * c.num_cu;
+    u32 *dcnt = c.alloc<u32>(nx);
+    i32 *dtouch = c.alloc<i32>(nx);
+    u32 *dlock = c.alloc<u32>(1);
+    PBNG_HIP(hipMemsetAsync(dcnt, 0, sizeof(u32) * nx, s));
+    PBNG_HIP(hipMemsetAsync(dlock, 0, sizeof(u32), s));
     unsigned char *alive_label = c.alloc<unsigned char>(G.n);
     u64 *sup_label = c.alloc<u64>(G.n);
     u64 *rmin = c.alloc<u64>(2);
@@ -1614,8 +1744,8 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
     const i32 ntiles = (i32)((nx + (i64(1) << tile_log) - 1) >> tile_log);
     const int tslots = c.num_cu;
     // active vertices above huge_w wedges take the key tiles; default: at
-    // least 4096 wedges per key tile on average
-    const u64 huge_w = o.tile_w == 0 ? std::max<u64>((u64)HUGE_W, (u64)ntiles * 4096u)
+    // least 16384 wedges per key tile on average
+    const u64 huge_w = o.tile_w == 0 ? std::max<u64>((u64)HUGE_W, (u64)ntiles * 16384u)
                                      : (o.tile_w < 0 ? ~0ull : (u64)o.tile_w);
     u32 *hoff = c.alloc<u32>(nx + 1);
     u32 *htotal = c.alloc<u32>(1);
@@ -1635,7 +1765,8 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
     pa.nnf = &ctl->nF2;
     pa.dcnt = dcnt;
     pa.dtouch = dtouch;
-    pa.dntouch = dntouch;
+    pa.dlock = dlock;
+    pa.hprobe = (o.flags & PBNG_F_SHORT_PROBE) ? 1 : H_PROBE;
     pa.ntiles = ntiles;
     pa.nx = nx;
     pa.tnext = &ctl->tnext;
@@ -1713,7 +1844,8 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
             PeelArgs ph = pt;
             ph.kc = c.kctr + PBNG_K_TIP_HRANGE;
             c.kbegin(PBNG_K_TIP_HRANGE, rs);
-            hipLaunchKernelGGL(k_tip_peel_hrange<H_LOGCAP>, dim3(std::min<i64>(slots, gridF * H_RANGE_MAX)), dim3(512), 0, rs,
+            hipLaunchKernelGGL((k_tip_peel_hrange<H_LOGCAP, H_BLOCK>), dim3(std::min<i64>(slots, gridF * H_RANGE_MAX)),
+                               dim3(H_BLOCK), 0, rs,
                                ph, 2, (const u32 *)hoff, (const u32 *)htotal);
             c.kend(PBNG_K_TIP_HRANGE, rs);
         }
@@ -1820,7 +1952,7 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
         if (level_mode) {
             u64 init2[2] = {~0ull, 0};
             PBNG_HIP(hipMemcpyAsync(rmin, init2, sizeof(init2), hipMemcpyHostToDevice, s));
-            hipLaunchKernelGGL(k_random_bound, dim3(gx), dim3(256), 0, s, (const u64 *)sup, (const unsigned char *)st, nx,
+            hipLaunchKernelGGL(k_random_bound, dim3(std::min(gx, 512)), dim3(256), 0, s, (const u64 *)sup, (const unsigned char *)st, nx,
                                rmin, rmin + 1);
             hipLaunchKernelGGL(k_level_bound, dim3(1), dim3(1), 0, s, ctl, (const u64 *)rmin, plev + pid);
             PBNG_LAUNCH_CHECK();
@@ -1828,7 +1960,7 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
             if (o.bound_rule == PBNG_BOUND_RANDOM) {
                 u64 init2[2] = {~0ull, 0};
                 PBNG_HIP(hipMemcpyAsync(rmin, init2, sizeof(init2), hipMemcpyHostToDevice, s));
-                hipLaunchKernelGGL(k_random_bound, dim3(gx), dim3(256), 0, s, (const u64 *)sup, (const unsigned char *)st, nx,
+                hipLaunchKernelGGL(k_random_bound, dim3(std::min(gx, 512)), dim3(256), 0, s, (const u64 *)sup, (const unsigned char *)st, nx,
                                    rmin, rmin + 1);
                 hipLaunchKernelGGL(k_random_pick, dim3(1), dim3(1), 0, s, ctl, (const u64 *)rmin, (const u64 *)(rmin + 1),
                                    (u64)o.seed, pid);
@@ -1839,7 +1971,7 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
                 weighted_select(c, that, w, st, ST_ALIVE, nx, nullptr, one_dev, P - pid, &ctl->s, &ctl->est_init);
                 u64 init2[2] = {~0ull, 0};
                 PBNG_HIP(hipMemcpyAsync(rmin, init2, sizeof(init2), hipMemcpyHostToDevice, s));
-                hipLaunchKernelGGL(k_random_bound, dim3(gx), dim3(256), 0, s, (const u64 *)sup, (const unsigned char *)st, nx,
+                hipLaunchKernelGGL(k_random_bound, dim3(std::min(gx, 512)), dim3(256), 0, s, (const u64 *)sup, (const unsigned char *)st, nx,
                                    rmin, rmin + 1);
                 hipLaunchKernelGGL(k_learned_guard, dim3(1), dim3(1), 0, s, ctl, (const u64 *)rmin);
                 PBNG_LAUNCH_CHECK();

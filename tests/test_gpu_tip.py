@@ -300,6 +300,22 @@ def test_tip_clustered_keys_overflow(ctx, clustered, P, tile_w):
     assert np.array_equal(gpu_tip(ctx, g, 0, P=P, tile_w=tile_w), eu)
 
 
+@pytest.mark.parametrize("tile_w", [-1, 0])
+def test_tip_short_probe_overflow_pass(ctx, cl_mid, clustered, tile_w):
+    """With a one-slot LDS probe limit most items of the key-range kernel
+    overflow and are counted again in the HBM counters that all workgroups
+    share under a lock: the result is unchanged."""
+    g, eu, ev = cl_mid
+    assert np.array_equal(gpu_tip(ctx, g, 0, P=150, tile_w=tile_w, flags=pb.F_SHORT_PROBE), eu)
+    # kernel-class counters (filled under kernel timing): the path ran
+    t = gpu_tip(ctx, g, 0, P=150, tile_w=tile_w, flags=pb.F_SHORT_PROBE | pb.binding.F_KERNEL_TIMING)
+    assert np.array_equal(t, eu)
+    assert ctx.stats()["kstat"]["tip_hrange"]["wedges"] > 0
+    assert np.array_equal(gpu_tip(ctx, g, 1, P=150, tile_w=tile_w, flags=pb.F_SHORT_PROBE), ev)
+    gc, ec = clustered
+    assert np.array_equal(gpu_tip(ctx, gc, 0, P=8, tile_w=tile_w, flags=pb.F_SHORT_PROBE), ec)
+
+
 def test_autotune_tip_and_cache(ctx, cl_mid):
     g, eu, ev = cl_mid
     dg = pb.DeviceGraph.from_graph(g)
