@@ -255,6 +255,25 @@ def test_tip_full_size_golden(ctx, wl, q):
     check_golden(rec, res, g.digest())
 
 
+@pytest.fixture(scope="module")
+def graph_100m():
+    return synth.config_graph("cl_5m_1m_100m")
+
+
+@pytest.mark.parametrize("rule", [pb.BOUND_PAPER, pb.BOUND_PLAIN])
+def test_tip_100m_edges_golden(ctx, graph_100m, rule):
+    """Side U of the 100M-edge Chung-Lu graph (5M x 1M, exponent 2.0, degree
+    cap 50k) at P = 150, in the benchmark's launch configuration (captured
+    rounds), against the oracle's full result, under the paper's range-bound
+    rule and the library's plain rule."""
+    rec = golden("cl_5m_1m_100m", "tip_u")
+    if rec is None:
+        pytest.skip("no stored oracle result")
+    dg = pb.DeviceGraph.from_graph(graph_100m)
+    res = u64(pb.tip(ctx, dg, 0, pb.make_opts(P=150, bound_rule=rule)))
+    check_golden(rec, res, graph_100m.digest())
+
+
 @pytest.mark.parametrize("cut", [-1, 16, 256])
 def test_tip_dense_tile_cutovers(ctx, cl_mid, cut):
     g, eu, ev = cl_mid
