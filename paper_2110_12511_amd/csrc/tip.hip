@@ -75,6 +75,8 @@ constexpr i64 HUGE_W = i64(1) << 16;
 constexpr int H_LOGCAP = 13;
 constexpr int H_BLOCK = 512;
 constexpr int H_WG_PER_CU = 2;
+// sets of HBM counters for the key-range kernel's overflow pass
+constexpr u32 H_OVF = 8;
 // active vertices with 2..PAIR_DMAX neighbours whose pairwise list
 // intersections cost less than 1 / PAIR_COST of their wedges take that path
 constexpr i64 PAIR_DMAX = 8;
@@ -103,10 +105,11 @@ struct PeelArgs {
     const u64 *bound;
     i32 *nf;
     u32 *nnf;
-    u32 *dcnt;           // key-range overflow: HBM counters (nx, zero between holders)
-    i32 *dtouch;         // their touched keys (nx)
-    u32 *dlock;          // the lock that serialises their holders
+    u32 *dcnt;           // key-range overflow: H_OVF sets of HBM counters (nx each, zero between holders)
+    i32 *dtouch;         // their touched keys (nx each)
+    u32 *dlock;          // one lock word per set
     i32 hprobe;          // LDS probe limit of the key-range path
+    const i32 *kspan;    // key-range bin: smallest and largest X id in the vertex's live lists
     i32 ntiles;
     i64 nx;
     u64 *tnext;          // key-tile item counter
@@ -492,6 +495,14 @@ __global__ __launch_bounds__(512) void k_tip_peel_tiled(PeelArgs a, int bin) {
 // finds its probe sequence full is counted again in HBM (see the kernel), so
 // the result is exact for any key skew.
 constexpr i64 H_RANGE_W = 4096;
+// At most H_RANGE_MAX ranges per vertex: a vertex above H_RANGE_MAX *
+// H_RANGE_W wedges has items of more than H_RANGE_W wedges, whose distinct
+// keys can still fill the table (its items then take the exact overflow
+// pass).  Finer ranges for those vertices cost more in repeated list
+// searches than the rare overflow (100M-edge graph: a cap of 256 or 65536
+// ranges took the range kernel from 2.66 to 2.93 s).  The cap also shrinks to
+// 2^31 / (vertices in the bin), so the item total of a round (32-bit) cannot
+// wrap.
 constexpr u32 H_RANGE_MAX = 64;
 constexpr int H_PROBE = 64;
 
@@ -500,6 +511,8 @@ __global__ __launch_bounds__(1024) void k_range_split(const i32 *items, const u3
                                                       u32 *total) {
     __shared__ i32 s_wave[1024 / WAVE];
     const u32 n = nbin[bin];
+    const u32 rcap0 = 0x80000000u / (n > 0 ? n : 1u);
+    const u64 rcap = rcap0 < 1u ? 1u : (rcap0 > H_RANGE_MAX ? H_RANGE_MAX : rcap0);
     u32 carry = 0;
     for (u32 base = 0; base < n; base += 1024) {
         const u32 i = base + threadIdx.x;
@@ -507,7 +520,7 @@ __global__ __launch_bounds__(1024) void k_range_split(const i32 *items, const u3
         if (i < n) {
             const u64 w = wi[items[i]];
             const u64 q = (w + (u64)H_RANGE_W - 1) / (u64)H_RANGE_W;
-            r = (i32)(q < 1 ? 1 : (q > H_RANGE_MAX ? H_RANGE_MAX : q));
+            r = (i32)(q < 1 ? 1 : (q > rcap ? rcap : q));
         }
         i32 tot;
         const i32 incl = block_incl_scan_i32<1024>(r, s_wave, tot);
@@ -530,6 +543,7 @@ struct RangeItem {
     u32 item;
     i32 x;
     u32 r, R;
+    i64 k0, k1;  // the item's key range
     i64 jb;
     i32 d;
     i64 base[WAVE];  // live list of neighbour j < 64: start and length
@@ -561,9 +575,19 @@ __device__ __forceinline__ void claim_range_item(const PeelArgs &a, int bin, con
             out->len[lane] = a.ylen[y];
         }
         if (lane == 0) {
+            const u32 r = it - off[lo], R = off[lo + 1] - off[lo];
+            // the R ranges divide the span of x's 2-hop ids; the first and
+            // last reach the ends of the key space, so they cover every key
+            i64 klo = a.kspan[2 * (i64)x], span = (i64)a.kspan[2 * (i64)x + 1] - klo + 1;
+            if (span <= 0) {
+                klo = 0;
+                span = a.nx;
+            }
             out->x = x;
-            out->r = it - off[lo];
-            out->R = off[lo + 1] - off[lo];
+            out->r = r;
+            out->R = R;
+            out->k0 = r == 0 ? 0 : klo + (i64)r * span / R;
+            out->k1 = r + 1 == R ? a.nx : klo + (i64)(r + 1) * span / R;
             out->jb = jb;
             out->d = d;
         }
@@ -579,7 +603,7 @@ __global__ __launch_bounds__(BLOCK) void k_tip_peel_hrange(PeelArgs a, int bin, 
     __shared__ i32 s_pre[BLOCK];
     __shared__ i64 s_moff[BLOCK];
     __shared__ i32 s_wave[BLOCK / WAVE];
-    __shared__ u32 s_ntouch, s_ovf;
+    __shared__ u32 s_ntouch, s_ovf, s_set;
     __shared__ RangeItem s_it[2];
     for (u32 i = threadIdx.x; i < CAP; i += BLOCK) {
         keys[i] = -1;
@@ -606,8 +630,8 @@ __global__ __launch_bounds__(BLOCK) void k_tip_peel_hrange(PeelArgs a, int bin, 
         if (item >= n) break;
         if (claimer) claim_range_item(a, bin, off, nh, n, &s_it[cur ^ 1]);
         const i32 x = ci.x;
-        const u32 r = ci.r, R = ci.R;
-        const i64 k0 = (i64)r * a.nx / R, k1 = (i64)(r + 1) * a.nx / R;
+        const u32 r = ci.r;
+        const i64 k0 = ci.k0, k1 = ci.k1;
         const i64 jb = ci.jb;
         const i32 d = ci.d;
         if (threadIdx.x == 0 && r == 0) {
@@ -616,18 +640,28 @@ __global__ __launch_bounds__(BLOCK) void k_tip_peel_hrange(PeelArgs a, int bin, 
         }
         // Pass 0 counts in the LDS table.  If a key finds its probe
         // sequence full, the item's LDS counts are dropped and pass 1
-        // counts the whole item again in the HBM counters, which all
-        // workgroups share under a lock (one item at a time; the counters
-        // are zero between holders), so the result is exact for any key skew.
+        // counts the whole item again in one of H_OVF sets of HBM counters
+        // that all workgroups share, each under a lock (one item per set at
+        // a time; a set's counters are zero between holders), so the result
+        // is exact for any key skew.
         bool redo = false;
+        u32 *gc = nullptr;
+        i32 *gt = nullptr;
         for (int pass = 0; pass < 2; ++pass) {
             if (pass == 1) {
                 if (!redo) break;  // block-uniform
                 if (threadIdx.x == 0) {
-                    while (atomicCAS(a.dlock, 0u, 1u) != 0u) __builtin_amdgcn_s_sleep(8);
+                    u32 k = blockIdx.x % H_OVF;
+                    while (atomicCAS(&a.dlock[k], 0u, 1u) != 0u) {
+                        k = (k + 1) % H_OVF;
+                        if (k == blockIdx.x % H_OVF) __builtin_amdgcn_s_sleep(8);
+                    }
                     __threadfence();
+                    s_set = k;
                 }
                 __syncthreads();
+                gc = a.dcnt + (i64)s_set * a.nx;
+                gt = a.dtouch + (i64)s_set * a.nx;
             }
             for (i32 cb = 0; cb < d; cb += BLOCK) {
                 const i32 j = cb + threadIdx.x;
@@ -665,10 +699,10 @@ __global__ __launch_bounds__(BLOCK) void k_tip_peel_hrange(PeelArgs a, int bin, 
                         for (int q = 0; q < UNR; ++q) {
                             const i32 xp = xq[q];
                             if (xp == x) continue;
-                            const u32 old = __hip_atomic_fetch_add(&a.dcnt[xp], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            const u32 old = __hip_atomic_fetch_add(&gc[xp], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                             if (old == 0) {
                                 const u32 t = atomicAdd(&s_ntouch, 1u);
-                                __hip_atomic_store(&a.dtouch[t], xp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                                __hip_atomic_store(&gt[t], xp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                             }
                         }
                         continue;
@@ -743,8 +777,8 @@ __global__ __launch_bounds__(BLOCK) void k_tip_peel_hrange(PeelArgs a, int bin, 
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
                         const u32 i = i0 + q * BLOCK;
-                        kk[q] = i < nt ? __hip_atomic_load(&a.dtouch[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : -1;
-                        cc[q] = kk[q] >= 0 ? __hip_atomic_exchange(&a.dcnt[kk[q]], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                        kk[q] = i < nt ? __hip_atomic_load(&gt[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : -1;
+                        cc[q] = kk[q] >= 0 ? __hip_atomic_exchange(&gc[kk[q]], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                                            : 0u;
                     }
                     apply_updates<4>(a, B, kk, cc, tl);
@@ -753,7 +787,7 @@ __global__ __launch_bounds__(BLOCK) void k_tip_peel_hrange(PeelArgs a, int bin, 
                 __syncthreads();
                 if (threadIdx.x == 0) {
                     s_ntouch = 0;
-                    atomicExch(a.dlock, 0u);
+                    atomicExch(&a.dlock[s_set], 0u);
                 }
             }
         }
@@ -825,9 +859,14 @@ __global__ void k_tip_peel_pairs(PeelArgs a, int bin) {
 
 // Wedges of each active vertex over the live lists (one wave per vertex),
 // their total (the batch rule's wedge count of the active set, Section 5.1),
-// and the work bins: small / medium LDS hash, LDS key tiles, HBM counters.
-__global__ void k_item_work(const i32 *F, const u32 *nF, const i64 *xrow, const i32 *xadj, const i32 *ylen, u64 *wi,
-                            u64 *wsum, i32 *lists, i64 stride, u32 *nbin, u64 huge_w) {
+// and the work bins: small / medium LDS hash, key ranges, key tiles, pairs.
+// A vertex of the key-range bin also gets the span [lo, hi] of the X ids in
+// its live lists, which its ranges divide: ids need not spread over the
+// whole key space (in a disjoint union of graphs every vertex's 2-hop ids lie
+// in its own graph's id block).
+__global__ void k_item_work(const i32 *F, const u32 *nF, const i64 *xrow, const i32 *xadj, const i64 *yrow,
+                            const i32 *yadj, const i32 *ylen, u64 *wi, u64 *wsum, i32 *lists, i64 stride, u32 *nbin,
+                            u64 huge_w, i32 *kspan) {
     const int lane = threadIdx.x & (WAVE - 1);
     const i64 wave = (blockIdx.x * (i64)blockDim.x + threadIdx.x) / WAVE;
     const i64 nwaves = (i64)gridDim.x * blockDim.x / WAVE;
@@ -858,6 +897,7 @@ __global__ void k_item_work(const i32 *F, const u32 *nF, const i64 *xrow, const 
             for (int dd = WAVE / 2; dd > 0; dd >>= 1) acc += __shfl_down(acc, dd, WAVE);
             pc = acc;
         }
+        int b = -1;
         if (lane == 0) {
             const bool pairs = s >= 2 && pc != ~0ull && PAIR_COST * pc < s;
             // the work estimate is what the chosen method walks
@@ -865,7 +905,6 @@ __global__ void k_item_work(const i32 *F, const u32 *nF, const i64 *xrow, const 
             wi[x] = sw;
             atomicAdd((unsigned long long *)wsum, (unsigned long long)sw);
             if (s >= 2) {
-                int b;
                 if (pairs) b = 4;
                 else if (s <= (u64)T_SMALL_W) b = 0;
                 else if (s <= (u64)T_MEDIUM_W) b = 1;
@@ -873,6 +912,29 @@ __global__ void k_item_work(const i32 *F, const u32 *nF, const i64 *xrow, const 
                 else b = 3;
                 u32 p = atomicAdd(&nbin[b], 1u);
                 lists[b * stride + p] = x;
+            }
+        }
+        b = __shfl(b, 0, WAVE);
+        if (b == 2) {
+            i32 lo = 0x7fffffff, hi = -1;
+            for (i64 j = jb + lane; j < je; j += WAVE) {
+                const i32 y = xadj[j];
+                const i32 l = ylen[y];
+                if (l > 0) {
+                    const i64 yb = yrow[y];
+                    const i32 h0 = yadj[yb], t0 = yadj[yb + l - 1];
+                    lo = h0 < lo ? h0 : lo;
+                    hi = t0 > hi ? t0 : hi;
+                }
+            }
+            for (int dd = WAVE / 2; dd > 0; dd >>= 1) {
+                const i32 ol = __shfl_xor(lo, dd, WAVE), oh = __shfl_xor(hi, dd, WAVE);
+                lo = ol < lo ? ol : lo;
+                hi = oh > hi ? oh : hi;
+            }
+            if (lane == 0) {
+                kspan[2 * (i64)x] = lo;
+                kspan[2 * (i64)x + 1] = hi;
             }
         }
     }
@@ -1711,11 +1773,12 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
     // key-range path: H_WG_PER_CU workgroups per CU, one shared set of
     // overflow counters
     const int slots = H_WG_PER_CU * c.num_cu;
-    u32 *dcnt = c.alloc<u32>(nx);
-    i32 *dtouch = c.alloc<i32>(nx);
-    u32 *dlock = c.alloc<u32>(1);
-    PBNG_HIP(hipMemsetAsync(dcnt, 0, sizeof(u32) * nx, s));
-    PBNG_HIP(hipMemsetAsync(dlock, 0, sizeof(u32), s));
+    u32 *dcnt = c.alloc<u32>((i64)H_OVF * nx);
+    i32 *dtouch = c.alloc<i32>((i64)H_OVF * nx);
+    u32 *dlock = c.alloc<u32>(H_OVF);
+    i32 *kspan = c.alloc<i32>(2 * nx);
+    PBNG_HIP(hipMemsetAsync(dcnt, 0, sizeof(u32) * H_OVF * nx, s));
+    PBNG_HIP(hipMemsetAsync(dlock, 0, sizeof(u32) * H_OVF, s));
     unsigned char *alive_label = c.alloc<unsigned char>(G.n);
     u64 *sup_label = c.alloc<u64>(G.n);
     u64 *rmin = c.alloc<u64>(2);
@@ -1766,6 +1829,7 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
     pa.dcnt = dcnt;
     pa.dtouch = dtouch;
     pa.dlock = dlock;
+    pa.kspan = kspan;
     pa.hprobe = (o.flags & PBNG_F_SHORT_PROBE) ? 1 : H_PROBE;
     pa.ntiles = ntiles;
     pa.nx = nx;
@@ -1786,8 +1850,8 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
     const int gx = grid_1d(nx);
     auto item_work = [&](i32 *cur) {
         hipLaunchKernelGGL(k_item_work, dim3(grid_1d((i64)nx * WAVE)), dim3(256), 0, s, (const i32 *)cur,
-                           (const u32 *)&ctl->nF, xrow, xadj, (const i32 *)ylen, wi, &ctl->wF, bins, nx, ctl->nbin,
-                           huge_w);
+                           (const u32 *)&ctl->nF, xrow, xadj, (const i64 *)yrow, (const i32 *)yadj, (const i32 *)ylen, wi,
+                           &ctl->wF, bins, nx, ctl->nbin, huge_w, kspan);
         PBNG_LAUNCH_CHECK();
     };
     // Levels of single-value partitions (~0 for ordinary ranges).  When what
@@ -1880,7 +1944,8 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
         }
         hipLaunchKernelGGL(k_next_round, dim3(1), dim3(1), 0, rs, ctl);
         hipLaunchKernelGGL(k_item_work, dim3(grid_1d((i64)nx * WAVE, 256, gcap)), dim3(256), 0, rs, (const i32 *)Fb,
-                           (const u32 *)&ctl->nF, xrow, xadj, (const i32 *)ylen, wi, &ctl->wF, bins, nx, ctl->nbin, huge_w);
+                           (const u32 *)&ctl->nF, xrow, xadj, (const i64 *)yrow, (const i32 *)yadj, (const i32 *)ylen, wi,
+                           &ctl->wF, bins, nx, ctl->nbin, huge_w, kspan);
         PBNG_LAUNCH_CHECK();
     };
     // Section 5.1: supports of the remaining graph by counting (the active

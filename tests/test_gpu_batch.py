@@ -150,14 +150,17 @@ def test_batch_4096_graphs_against_oracle(ctx):
     gs = synth.mixed_graphs(range(rec["n_graphs"]), 1e3, 1e6)
     for i, g in enumerate(gs):
         assert g.digest()[:16] == ent[str(i)]["graph"], i
+    print(f"[4096] {len(gs)} graphs drawn", flush=True)
     rule = pb.BOUND_LEARNED if predictor.install(ctx) else pb.BOUND_PLAIN
     dgs = [pb.DeviceGraph.from_graph(g) for g in gs]
     del gs
     res = pb.tip_batch(ctx, dgs, 0, pb.make_opts(bound_rule=rule))
+    print(f"[4096] tip batch {ctx.stats()['ms_total']:.0f} ms", flush=True)
     for i, r in enumerate(res):
         assert digest(u64(r))[:16] == ent[str(i)]["tip_u"], i
     del res
     res = pb.wing_batch(ctx, dgs, pb.make_opts(bound_rule=rule))
+    print(f"[4096] wing batch {ctx.stats()['ms_total']:.0f} ms", flush=True)
     checked = 0
     for i, r in enumerate(res):
         if "wing" in ent[str(i)]:
