@@ -343,8 +343,10 @@ def main():
         bt, bms = ctx.autotune(dg[big], 0)
         bw, wms = ctx.autotune(dg[big], 2)
         tune = dict(dense_cut=bt.dense_cut, tile_w=bt.tile_w)
-        tuned = dict(graph=graphs[big].name, tip=dict(dense_cut=bt.dense_cut, tile_w=bt.tile_w, P=bt.P, ms=round(bms, 2)),
-                     wing=dict(dense_cut=bw.dense_cut, P=bw.P, ms=round(wms, 2)))
+        tuned = dict(graph=graphs[big].name,
+                     tip=dict(dense_cut=bt.dense_cut, tile_w=bt.tile_w, recount_w=bt.recount_w, P=bt.P,
+                              ms=round(bms, 2)),
+                     wing=dict(dense_cut=bw.dense_cut, wide_work=bw.wide_work, P=bw.P, ms=round(wms, 2)))
         log(f"[bench] autotuned on {graphs[big].name}: {tuned}")
 
     for i in range(args.warmup):

@@ -141,8 +141,9 @@ typedef struct {
     int32_t tile_w;     /* coarse-grained tip rounds: active vertices with
                            more live wedges than this count in LDS key tiles,
                            others in LDS hash ranges; 0 = library default
-                           (the larger of 2^16 and 4096 per 2^16-vertex tile
-                           of the side), negative = never (schedule only)    */
+                           (the larger of 2^16 and 16384 per 2^16-vertex
+                           tile of the side), negative = never (schedule
+                           only)                                             */
     int32_t batch_edges;/* batch calls: most edges packed into one union
                            graph; 0 = library default (2^26)                 */
     int32_t wide_work;  /* wing: fine-grained work above which a partition
@@ -299,11 +300,15 @@ int pbng_wing_batch(pbng_ctx *ctx, const pbng_csr *g, int32_t ng,
  *
  * Times one call of `kind` (0: tip numbers of side U, 1: of side V, 2: wing
  * numbers) on g under schedule settings picked by coordinate descent from
- * *base (NULL = defaults): first the int8 hub cut-over dense_cut in
- * {-1 (off), 256, 1024, 4096}, then (tip) the key-tile threshold tile_w in
- * {2^16, 2^18, 2^20, -1 (never)}, then the partition count P: the base
- * value against P0/2 and 2 P0 (P0 = base P, else 150 for tip and 400 for
- * wing).  One untimed warm
+ * *base (NULL = defaults): (tip, when the base rule is PLAIN or PAPER) the
+ * bound rule, PLAIN against PAPER; the int8 hub cut-over dense_cut in
+ * {-1 (off), 256, 1024, 4096}; (tip) the key-tile threshold tile_w in
+ * {2^16, 2^18, 2^20, -1 (never)} and the recount bound recount_w in
+ * {0 (Section 5.1), -1 (never)}; (wing) the device-wide partition threshold
+ * wide_work, its default 2^24 against {2^22, 2^26, -1 (never)}; then the
+ * partition count P:
+ * the base value against P0/2 and 2 P0 (P0 = base P, else 150 for tip and
+ * 400 for wing).  One untimed warm
  * run precedes the timed ones; each setting is timed once.  The fastest
  * setting goes to *best and its time in ms to *ms_best (may be NULL).  The
  * context caches it under the graph's signature (n_u, n_v, m, largest

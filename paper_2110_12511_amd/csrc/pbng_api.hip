@@ -648,8 +648,20 @@ int pbng_autotune(pbng_ctx *x, const pbng_csr *g, int32_t kind, const pbng_opts 
             }
             cur.*field = win;
         };
+        // tip: the paper's range rule against the library's plain rule (a
+        // caller's learned or random rule is kept)
+        if (kind != 2 && (cur.bound_rule == PBNG_BOUND_PLAIN || cur.bound_rule == PBNG_BOUND_PAPER))
+            try_knob(&pbng_opts::bound_rule, {PBNG_BOUND_PLAIN, PBNG_BOUND_PAPER});
         try_knob(&pbng_opts::dense_cut, {-1, 256, 1024, 4096});
-        if (kind != 2) try_knob(&pbng_opts::tile_w, {1 << 16, 1 << 18, 1 << 20, -1});
+        if (kind != 2) {
+            try_knob(&pbng_opts::tile_w, {1 << 16, 1 << 18, 1 << 20, -1});
+            // the Section 5.1 recount bound against never recounting
+            try_knob(&pbng_opts::recount_w, {0, -1});
+        } else {
+            // wing: fine-grained work above which a partition is peeled
+            // device-wide
+            try_knob(&pbng_opts::wide_work, {1 << 22, 1 << 26, -1});
+        }
         const int32_t p0 = cur.P > 0 ? cur.P : (kind == 2 ? 400 : 150);
         try_knob(&pbng_opts::P, {std::max(1, p0 / 2), p0 * 2});
         *best = cur;

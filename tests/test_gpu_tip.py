@@ -340,8 +340,13 @@ def test_autotune_tip_and_cache(ctx, cl_mid):
     dg = pb.DeviceGraph.from_graph(g)
     best, ms = ctx.autotune(dg, 0, pb.make_opts(P=40))
     assert ms > 0 and best.P in (20, 40, 80)
+    assert best.bound_rule in (pb.BOUND_PLAIN, pb.BOUND_PAPER) and best.recount_w in (0, -1)
     assert np.array_equal(u64(pb.tip(ctx, dg, 0, best)), eu)
     best2, ms2 = ctx.autotune(dg, 0, pb.make_opts(P=40))
-    assert (best2.P, best2.dense_cut, best2.tile_w, ms2) == (best.P, best.dense_cut, best.tile_w, ms)
+    assert (best2.P, best2.dense_cut, best2.tile_w, best2.bound_rule, best2.recount_w, ms2) == \
+        (best.P, best.dense_cut, best.tile_w, best.bound_rule, best.recount_w, ms)
+    # a caller's learned rule is kept
+    best3, _ = ctx.autotune(dg, 1, pb.make_opts(P=40, bound_rule=pb.BOUND_LEARNED))
+    assert best3.bound_rule == pb.BOUND_LEARNED
     bv, _ = ctx.autotune(dg, 1)
     assert np.array_equal(u64(pb.tip(ctx, dg, 1, bv)), ev)

@@ -101,7 +101,7 @@ def test_autotune_wing(ctx, cl_wing):
     g, exp = cl_wing
     dg = pb.DeviceGraph.from_graph(g)
     best, ms = ctx.autotune(dg, 2)
-    assert ms > 0
+    assert ms > 0 and best.wide_work in (0, 1 << 22, 1 << 26, -1)
     assert np.array_equal(u64(pb.wing(ctx, dg, best)), exp)
 
 
