@@ -398,8 +398,10 @@ __global__ __launch_bounds__(BLOCK) void k_count_hash(CountArgs a) {
 }
 
 template <int MODE>
-__global__ __launch_bounds__(256) void k_count_dense(CountArgs a) {
-    constexpr int BLOCK = 256;
+__global__ __launch_bounds__(1024) void k_count_dense(CountArgs a) {
+    // one workgroup per HBM counter slice (the slices bound the grid), so the
+    // workgroup is wide: 16 waves per CU hide the scattered counter latency
+    constexpr int BLOCK = 1024;
     __shared__ i32 s_pre[BLOCK];
     __shared__ i64 s_moff[BLOCK];
     __shared__ u64 s_agg[BLOCK];
@@ -711,7 +713,7 @@ static void launch_all(Ctx &c, const DevGraph &G, CountArgs a, const Bins &b) {
         a.starts = b.lists + 3 * G.n;
         a.nstarts = b.cnt[3];
         a.next = next + 3;
-        hipLaunchKernelGGL(k_count_dense<MODE>, dim3(slots), dim3(256), 0, c.stream, a);
+        hipLaunchKernelGGL(k_count_dense<MODE>, dim3(slots), dim3(1024), 0, c.stream, a);
         PBNG_LAUNCH_CHECK();
     }
     if constexpr (MODE == M_XSIDE || MODE == M_VERTEX) {
@@ -733,7 +735,7 @@ static void launch_all(Ctx &c, const DevGraph &G, CountArgs a, const Bins &b) {
         a.nstarts = b.cnt[1];
         a.next = next + 1;
         int grid = (int)std::min<i64>(b.cnt[1], (i64)c.num_cu * 2);
-        hipLaunchKernelGGL((k_count_hash<256, 13, MODE>), dim3(grid), dim3(256), 0, c.stream, a);
+        hipLaunchKernelGGL((k_count_hash<512, 13, MODE>), dim3(grid), dim3(512), 0, c.stream, a);
         PBNG_LAUNCH_CHECK();
     }
     if (b.cnt[0]) {
