@@ -486,8 +486,9 @@ __global__ __launch_bounds__(512) void k_tip_peel_tiled(PeelArgs a, int bin) {
 
 // Heavy active vertices whose wedges are many but whose degree is small (a
 // few neighbours with long lists, the common case under power-law degrees):
-// the wedges of x are cut into R_x = ceil(w_x / H_RANGE_W) ranges of the X
-// key space, and one work item is one (vertex, range) pair.  Each range
+// the wedges of x are cut into R_x = ceil(w_x / H_RANGE_W) ranges of the
+// span of X ids in its live lists (the first and last range reach the ends
+// of the key space), and one work item is one (vertex, range) pair.  Each range
 // counts c(x, x') in an LDS hash table of 2^LOGCAP slots (twice the wedges
 // of an item whose keys are spread evenly, and small enough for two
 // workgroups per CU); the run of every neighbour list inside the range is
@@ -1770,8 +1771,8 @@ void tip_decompose(Ctx &c, const DevGraph &G, int side, const pbng_opts &o, u64 
         PBNG_HIP(hipMemcpyAsync(&ctl->scale, &one, sizeof(double), hipMemcpyHostToDevice, s));
     }
     // dense scratch for heavy active vertices
-    // key-range path: H_WG_PER_CU workgroups per CU, one shared set of
-    // overflow counters
+    // key-range path: H_WG_PER_CU workgroups per CU, H_OVF shared sets of
+    // overflow counters, the id span of each of its vertices
     const int slots = H_WG_PER_CU * c.num_cu;
     u32 *dcnt = c.alloc<u32>((i64)H_OVF * nx);
     i32 *dtouch = c.alloc<i32>((i64)H_OVF * nx);
