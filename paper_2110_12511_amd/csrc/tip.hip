@@ -361,7 +361,8 @@ __global__ __launch_bounds__(BLOCK) void k_tip_peel_hash(PeelArgs a, int bin) {
 // of x whose far end lies in a key tile [r0, r0 + 2^TLOG) form one run of
 // every list.  A work item is one (vertex, tile) pair, so the tiles of one
 // vertex run on different workgroups at once: each finds the run of every
-// neighbour's list by binary search and counts the run's wedges in LDS.  A
+// neighbour's list by the lockstep search of run_bounds and counts the run's
+// wedges in LDS (the last wave claims the next item meanwhile).  A
 // count c(x, x') never exceeds the degree of x, so when every degree of the
 // graph is below 2^16 (PACK) two 16-bit counters share a word and a tile
 // covers 2^16 keys; otherwise each key has a 32-bit counter and a tile
