@@ -48,7 +48,9 @@ extern "C" {
 #define PBNG_E_NOMEM (-3)       /* device allocation failed                   */
 #define PBNG_E_DEVICE (-4)      /* HIP runtime error (see pbng_last_error)    */
 #define PBNG_E_OVERFLOW (-5)    /* size beyond the library's index widths     */
-#define PBNG_E_TIMEOUT (-6)     /* a bounded device wait did not finish       */
+#define PBNG_E_TIMEOUT (-6)     /* reserved: no call of this version returns
+                                   it (no device wait here is bounded by
+                                   time; every wait ends by construction)  */
 #define PBNG_E_UNSUPPORTED (-7) /* option not available                       */
 
 typedef struct pbng_ctx pbng_ctx;
