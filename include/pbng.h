@@ -91,8 +91,11 @@ typedef enum {
 #define PBNG_F_NO_DYNAMIC 0x1   /* keep peeled entities in the lists (no
                                    dynamic graph updates, Section 5.2)     */
 #define PBNG_F_NO_BATCH 0x2     /* tip: never recount; wing: per-edge update
-                                   instead of bloom-aggregated batches
-                                   (Section 5.1)                            */
+                                   in the coarse-grained rounds (every peeled
+                                   edge walks its blooms) instead of one
+                                   bloom-aggregated update per bloom
+                                   (Section 5.1; with PBNG_F_NO_DYNAMIC the
+                                   PBNG-- ablation of Section 6)            */
 #define PBNG_F_NO_DENSE_TILE 0x4 /* counting: scalar path for hub pairs too */
 #define PBNG_F_KERNEL_TIMING 0x8 /* time kernel classes with HIP events on
                                     the context stream (fills

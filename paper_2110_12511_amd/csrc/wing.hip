@@ -131,10 +131,86 @@ __global__ void w_links(const i32 *F, const u32 *nF, const i64 *eoff, const i32 
     t.flush(kc, nullptr);
 }
 
+// Unbatched form of the round (the PBNG-- ablation, Section 6.3.2): the
+// twin updates and bloom counts of w_links, but every acting link then walks
+// its bloom itself and takes one butterfly from both edges of every alive
+// pair, instead of each touched bloom subtracting its count once (w_blooms
+// then only drops pairs and lowers k_B).  The totals per edge are the same,
+// count[B] per bloom; the work is one bloom walk per peeled pair.  One wave
+// per active edge: lanes evaluate 64 links, then the wave walks the bloom of
+// each acting one.
+__global__ void w_links_each(const i32 *F, const u32 *nF, const i64 *eoff, const i32 *ebloom, const i32 *etwin,
+                             const unsigned char *st, const u32 *bk, u32 *bcount, i32 *touched, const i64 *boff,
+                             const u32 *blen, const i32 *bedge, u64 *sup, WingCtl *ctl, i32 *F2, KCounters *kc) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const i64 wave = (blockIdx.x * (i64)blockDim.x + threadIdx.x) / WAVE;
+    const i64 nwaves = (i64)gridDim.x * blockDim.x / WAVE;
+    const u32 n = *nF;
+    const u64 B = ctl->bound;
+    Tally t;
+    u64 upd = 0;
+    for (i64 i = wave; i < n; i += nwaves) {
+        const i32 e = F[i];
+        const i64 q1 = eoff[e + 1];
+        for (i64 q0 = eoff[e]; q0 < q1; q0 += WAVE) {
+            const i64 q = q0 + lane;
+            bool act = false;
+            i32 b = -1;
+            if (q < q1) {
+                ++t.wedges;
+                const i32 et = etwin[q];
+                const unsigned char s = st[et];
+                // pair dropped earlier, or both active and the larger twin acts
+                if (s != WS_PEELED && !(s == WS_ACTIVE && et > e)) {
+                    act = true;
+                    b = ebloom[q];
+                    if (s == WS_ALIVE) {
+                        const u32 kb = bk[b];
+                        const u64 d = kb > 1 ? (u64)kb - 1 : 0;
+                        if (d) {
+                            w_dec(sup, et, d, B, F2, &ctl->nF2);
+                            ++upd;
+                        }
+                    }
+                    if (atomicAdd(&bcount[b], 1u) == 0) {
+                        u32 p = atomicAdd(&ctl->ntouch, 1u);
+                        touched[p] = b;
+                        ++t.segments;
+                    }
+                }
+            }
+            u64 bal = __ballot(act);
+            while (bal) {
+                const int k = __builtin_ctzll(bal);
+                bal &= bal - 1;
+                const i32 bb = __shfl(b, k, WAVE);
+                const i64 base = boff[bb];
+                const i32 len = (i32)blen[bb];
+                for (i32 pp = lane; pp < len; pp += WAVE) {
+                    const i32 e1 = bedge[2 * (base + pp)], e2 = bedge[2 * (base + pp) + 1];
+                    if (st[e1] == WS_ALIVE && st[e2] == WS_ALIVE) {
+                        w_dec(sup, e1, 1, B, F2, &ctl->nF2);
+                        w_dec(sup, e2, 1, B, F2, &ctl->nF2);
+                        upd += 2;
+                    }
+                }
+            }
+        }
+    }
+    t.atomics = upd;
+    for (int d = WAVE / 2; d > 0; d >>= 1) upd += __shfl_down(upd, d, WAVE);
+    if (lane == 0 && upd) atomicAdd((unsigned long long *)&ctl->updates, (unsigned long long)upd);
+    u64 lk = t.wedges;
+    for (int d = WAVE / 2; d > 0; d >>= 1) lk += __shfl_down(lk, d, WAVE);
+    if (lane == 0 && lk) atomicAdd((unsigned long long *)&ctl->links, (unsigned long long)lk);
+    t.flush(kc, nullptr);
+}
+
 // One wave per touched bloom: drop pairs with a non-alive edge (in place,
-// order kept), subtract count[B] from both edges of every surviving pair.
+// order kept), subtract count[B] from both edges of every surviving pair
+// (unless the round's links already did, decrement = 0).
 __global__ void w_blooms(const i32 *touched, const u32 *ntouch, const i64 *boff, u32 *blen, u32 *bk, u32 *bcount,
-                         i32 *bedge, const unsigned char *st, u64 *sup, WingCtl *ctl, i32 *F2, int dynamic,
+                         i32 *bedge, const unsigned char *st, u64 *sup, WingCtl *ctl, i32 *F2, int dynamic, int decrement,
                          KCounters *kc) {
     const int lane = threadIdx.x & (WAVE - 1);
     const i64 wave = (blockIdx.x * (i64)blockDim.x + threadIdx.x) / WAVE;
@@ -160,7 +236,7 @@ __global__ void w_blooms(const i32 *touched, const u32 *ntouch, const i64 *boff,
                 keep = st[e1] == WS_ALIVE && st[e2] == WS_ALIVE;
                 t.wedges += 2;
             }
-            if (keep) {
+            if (keep && decrement) {
                 w_dec(sup, e1, cnt, B, F2, &ctl->nF2);
                 w_dec(sup, e2, cnt, B, F2, &ctl->nF2);
                 upd += 2;
@@ -865,8 +941,8 @@ void wing_decompose(Ctx &c, const DevGraph &G, const pbng_opts &o, u64 *theta) {
     const i64 m = G.m;
     if (m == 0) return;
     const bool dynamic = !(o.flags & PBNG_F_NO_DYNAMIC);
-    if (o.flags & PBNG_F_NO_BATCH)
-        throw Error(PBNG_E_UNSUPPORTED, "wing decomposition without bloom-batched updates is not built");
+    // PBNG--: per-edge bloom walks instead of bloom-aggregated batches
+    const bool unbatched = (o.flags & PBNG_F_NO_BATCH) != 0;
     const double t0 = wnow_ms();
 
     // ---- per-edge counting and BE-Index
@@ -918,13 +994,22 @@ void wing_decompose(Ctx &c, const DevGraph &G, const pbng_opts &o, u64 *theta) {
     // partition find an empty active set and do nothing.
     const bool host_rounds = (o.flags & PBNG_F_HOST_ROUNDS) != 0;
     const int gfix = c.num_cu * 8;
+    auto links = [&](hipStream_t rs, dim3 grid, i32 *Fa, i32 *Fb) {
+        if (unbatched)
+            hipLaunchKernelGGL(w_links_each, grid, dim3(256), 0, rs, (const i32 *)Fa, (const u32 *)&ctl->nF,
+                               (const i64 *)I.eoff, (const i32 *)I.ebloom, (const i32 *)I.etwin, (const unsigned char *)st,
+                               (const u32 *)bk, bcount, touched, (const i64 *)I.boff, (const u32 *)blen,
+                               (const i32 *)cedge, sup, ctl, Fb, c.kctr + PBNG_K_WING_CD);
+        else
+            hipLaunchKernelGGL(w_links, grid, dim3(256), 0, rs, (const i32 *)Fa, (const u32 *)&ctl->nF, (const i64 *)I.eoff,
+                               (const i32 *)I.ebloom, (const i32 *)I.etwin, (const unsigned char *)st, (const u32 *)bk,
+                               bcount, touched, sup, ctl, Fb, c.kctr + PBNG_K_WING_CD);
+    };
     auto round_fixed = [&](hipStream_t rs, i32 *Fa, i32 *Fb) {
-        hipLaunchKernelGGL(w_links, dim3(gfix), dim3(256), 0, rs, (const i32 *)Fa, (const u32 *)&ctl->nF, (const i64 *)I.eoff,
-                           (const i32 *)I.ebloom, (const i32 *)I.etwin, (const unsigned char *)st, (const u32 *)bk, bcount,
-                           touched, sup, ctl, Fb, c.kctr + PBNG_K_WING_CD);
+        links(rs, dim3(gfix), Fa, Fb);
         hipLaunchKernelGGL(w_blooms, dim3(gfix), dim3(256), 0, rs, (const i32 *)touched, (const u32 *)&ctl->ntouch,
                            (const i64 *)I.boff, blen, bk, bcount, cedge, (const unsigned char *)st, sup, ctl, Fb,
-                           dynamic ? 1 : 0, c.kctr + PBNG_K_WING_CD);
+                           dynamic ? 1 : 0, unbatched ? 0 : 1, c.kctr + PBNG_K_WING_CD);
         hipLaunchKernelGGL(w_retire, dim3(c.num_cu * 2), dim3(256), 0, rs, (const i32 *)Fa, (const u32 *)&ctl->nF, st,
                            (const u64 *)init, ctl);
         hipLaunchKernelGGL(w_activate, dim3(c.num_cu * 2), dim3(256), 0, rs, (const i32 *)Fb, (const u32 *)&ctl->nF2, st,
@@ -1005,13 +1090,11 @@ void wing_decompose(Ctx &c, const DevGraph &G, const pbng_opts &o, u64 *theta) {
                     break;
                 }
                 c.kbegin(PBNG_K_WING_CD);
-                hipLaunchKernelGGL(w_links, dim3(gw), dim3(256), 0, s, (const i32 *)F, (const u32 *)&ctl->nF,
-                                   (const i64 *)I.eoff, (const i32 *)I.ebloom, (const i32 *)I.etwin, (const unsigned char *)st,
-                                   (const u32 *)bk, bcount, touched, sup, ctl, F2, c.kctr + PBNG_K_WING_CD);
+                links(s, dim3(gw), F, F2);
                 PBNG_LAUNCH_CHECK();
                 hipLaunchKernelGGL(w_blooms, dim3(grid_1d((i64)std::min<i64>(nbl, (i64)nF * 64) * WAVE)), dim3(256), 0, s,
                                    (const i32 *)touched, (const u32 *)&ctl->ntouch, (const i64 *)I.boff, blen, bk, bcount,
-                                   cedge, (const unsigned char *)st, sup, ctl, F2, dynamic ? 1 : 0,
+                                   cedge, (const unsigned char *)st, sup, ctl, F2, dynamic ? 1 : 0, unbatched ? 0 : 1,
                                    c.kctr + PBNG_K_WING_CD);
                 c.kend(PBNG_K_WING_CD);
                 PBNG_LAUNCH_CHECK();

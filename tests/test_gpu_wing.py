@@ -66,6 +66,26 @@ def test_wing_no_dynamic_and_random_bounds(ctx, cl_wing):
         assert np.array_equal(gpu_wing(ctx, g, P=80, bound_rule=pb.BOUND_RANDOM, seed=seed), exp)
 
 
+@pytest.mark.parametrize("flags", [pb.F_NO_BATCH, pb.F_NO_DYNAMIC | pb.F_NO_BATCH])
+def test_wing_unbatched_updates(ctx, cl_wing, flags):
+    """PBNG--: every peeled edge walks its blooms itself instead of each
+    touched bloom subtracting its count once; same wing numbers, captured
+    and host-driven rounds, and more support updates than the batched
+    form."""
+    g, exp = cl_wing
+    assert np.array_equal(gpu_wing(ctx, g, P=50), exp)
+    batched = ctx.stats()["updates"]
+    assert np.array_equal(gpu_wing(ctx, g, P=50, flags=flags), exp)
+    assert ctx.stats()["updates"] > batched
+    assert np.array_equal(gpu_wing(ctx, g, P=50, flags=flags | pb.F_HOST_ROUNDS), exp)
+    for s in range(20):
+        rng = np.random.default_rng(700 + s)
+        gs = synth.random_small(int(rng.integers(2, 10)), int(rng.integers(2, 10)), float(rng.choice([0.5, 0.9])), seed=s)
+        assert np.array_equal(gpu_wing(ctx, gs, P=3, flags=flags), oracle.wing(gs)), gs.name
+    k = synth.from_edges(3, 3, [(0, 0), (0, 1), (1, 0), (1, 1), (2, 2)])
+    assert gpu_wing(ctx, k, P=2, flags=flags).tolist() == [1, 1, 1, 1, 0]
+
+
 def test_wing_stats_be_index(ctx, cl_wing):
     g, exp = cl_wing
     gpu_wing(ctx, g, P=400)
