@@ -51,7 +51,8 @@ extern "C" {
 #define PBNG_E_TIMEOUT (-6)     /* reserved: no call of this version returns
                                    it (no device wait here is bounded by
                                    time; every wait ends by construction)  */
-#define PBNG_E_UNSUPPORTED (-7) /* option not available                       */
+#define PBNG_E_UNSUPPORTED (-7) /* reserved: option not available (every
+                                   option of this version is built)        */
 
 typedef struct pbng_ctx pbng_ctx;
 
