@@ -133,10 +133,10 @@ def test_uneven_batch_matches_single_calls(ctx):
 
 def test_batch_4096_graphs_against_oracle(ctx):
     """The 4096-graph batch (edge counts log-uniform in 1e3 .. 1e6, half
-    Erdos-Renyi, half Chung-Lu): tip numbers of side U of every graph and
-    wing numbers of every graph the stored oracle results cover (all graphs
-    up to 3e5 edges and a seeded sample of larger ones), one batched call
-    each under learned bounds, against the oracle's SHA-256 prefixes."""
+    Erdos-Renyi, half Chung-Lu): tip numbers of side U and wing numbers of
+    every graph the stored oracle results cover (all 4096 for both), one
+    batched call each under learned bounds, against the oracle's SHA-256
+    prefixes."""
     import json
     import os
 
